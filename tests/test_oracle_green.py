@@ -1,0 +1,159 @@
+"""Pins of the oracle's discrete Green tensor (Sec. 2, eqs. 1-3).
+
+The tensor is checked against properties the mathematics fixes, with every
+auxiliary operator (stiffness, finite differences) rebuilt here from its
+definition rather than taken from the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import alm, dg
+
+
+LAM0, MU0 = 4.0, 2.0
+
+
+def C_iso(lam, mu):
+    """Isotropic plane-strain stiffness as an explicit 2x2x2x2 array."""
+    C = np.zeros((2, 2, 2, 2))
+    for i in range(2):
+        for j in range(2):
+            for k in range(2):
+                for l in range(2):
+                    C[i, j, k, l] = (lam * (i == j) * (k == l)
+                                     + mu * ((i == k) * (j == l) + (i == l) * (j == k)))
+    return C
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_projection_identity(L):
+    """G C0 G = -G: G is minus the C0-orthogonal projector onto compatible fields."""
+    G = dg.green_on_grid(L, LAM0, MU0)
+    GCG = np.einsum("...ijkl,klmn,...mnpq->...ijpq", G, C_iso(LAM0, MU0), G)
+    assert np.abs(GCG + G).max() < 1e-14 * max(1.0, np.abs(G).max())
+
+
+def test_hermitian_symmetry_stated_in_paper():
+    """G_ijkl = conj(G_klij) (Sec. 2, the paragraph after eq. 3)."""
+    G = dg.green_on_grid(16, LAM0, MU0)
+    assert np.abs(G - np.conj(np.einsum("...ijkl->...klij", G))).max() < 1e-15
+
+
+def test_lacks_major_symmetry_and_is_complex():
+    """The paper notes the nonzero imaginary part breaks major symmetry."""
+    G = dg.green_on_grid(16, LAM0, MU0)
+    assert np.abs(G.imag).max() > 1e-2
+    assert np.abs(G - np.einsum("...ijkl->...klij", G)).max() > 1e-2
+
+
+def test_conjugate_at_minus_q_and_real_at_self_conjugate_points():
+    L = 16
+    K = dg.half_spectrum_k(L)
+    Kminus = dg.half_spectrum_k(L, True, True)
+    G = dg.green_tensor(K, LAM0, MU0)
+    Gm = dg.green_tensor(Kminus, LAM0, MU0)
+    assert np.abs(Gm - np.conj(G)).max() < 1e-15
+    for m2 in (0, L // 2):
+        for m1 in (0, L // 2):
+            assert np.abs(G[m2, m1].imag).max() < 1e-15
+
+
+def _fwd_diff_strain(u):
+    """eps_ij = [u_j(x+e^i) - u_j(x) + u_i(x+e^j) - u_i(x)] / 2, eq. 1; u: (L, L, 2)."""
+    L = u.shape[0]
+    du = np.zeros((L, L, 2, 2))   # du[..., i, j] = u_j(x + e^i) - u_j(x)
+    du[..., 0, :] = np.roll(u, -1, axis=1) - u     # direction 1 = axis 1
+    du[..., 1, :] = np.roll(u, -1, axis=0) - u     # direction 2 = axis 0
+    return 0.5 * (du + np.swapaxes(du, -1, -2))
+
+
+def _bwd_div(s):
+    """sum_j s_ij(x) - s_ij(x - e^j), eq. 1; s: (L, L, 2, 2)."""
+    return (s[..., :, 0] - np.roll(s[..., :, 0], 1, axis=1)
+            + s[..., :, 1] - np.roll(s[..., :, 1], 1, axis=0))
+
+
+def _embed(a2):
+    a = np.zeros(a2.shape[:-2] + (3, 3))
+    a[..., :2, :2] = a2
+    return a
+
+
+@pytest.mark.parametrize("L", [8, 12, 16])
+def test_compatible_field_is_reproduced(L):
+    """For eps = forward-difference strain of any u: e = G * (-C0:eps) = eps.
+
+    Pins the momentum convention k_j = 2 sin(q/2) e^{iq/2} against eq. 1, the
+    DFT sign convention, and the sign of G."""
+    rng = np.random.default_rng(L)
+    u = rng.normal(size=(L, L, 2))
+    eps = _fwd_diff_strain(u)
+    s = alm.Solver(np.zeros((L, L), np.uint8), alm.Params(L=L, mu0=MU0, lam0=LAM0))
+    tau2 = -np.einsum("klmn,...mn->...kl", C_iso(LAM0, MU0), eps)
+    e = s.green_step(_embed(tau2), (0.0, 0.0, 0.0))
+    assert np.abs(e[..., :2, :2] - eps).max() < 1e-12
+    assert np.abs(e[..., 2, :]).max() == 0.0
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_green_step_gives_equilibrium_and_mean(L):
+    """sigma = C0:e + tau with e = E + G*tau is divergence-free with the
+    backward differences of eq. 1 at every pixel, and <e> = E."""
+    rng = np.random.default_rng(100 + L)
+    t = rng.normal(size=(L, L, 2, 2))
+    tau2 = 0.5 * (t + np.swapaxes(t, -1, -2))
+    E = (0.3, -0.2, 0.15)
+    s = alm.Solver(np.zeros((L, L), np.uint8), alm.Params(L=L, mu0=MU0, lam0=LAM0))
+    e = s.green_step(_embed(tau2), E)
+    sig = np.einsum("klmn,...mn->...kl", C_iso(LAM0, MU0), e[..., :2, :2]) + tau2
+    assert np.abs(_bwd_div(sig)).max() < 1e-12
+    np.testing.assert_allclose(e.mean(axis=(0, 1))[:2, :2], [[0.3, 0.15], [0.15, -0.2]], atol=1e-14)
+
+
+def test_compatibility_of_green_output():
+    """G*tau is a forward-difference strain: its Saint-Venant incompatibility
+    (the discrete curl-curl built from forward differences) vanishes."""
+    L = 16
+    rng = np.random.default_rng(7)
+    t = rng.normal(size=(L, L, 2, 2))
+    tau2 = 0.5 * (t + np.swapaxes(t, -1, -2))
+    s = alm.Solver(np.zeros((L, L), np.uint8), alm.Params(L=L, mu0=MU0, lam0=LAM0))
+    e = s.green_step(_embed(tau2), (0.0, 0.0, 0.0))[..., :2, :2]
+    # eps11 = D1 u1, eps22 = D2 u2, 2 eps12 = D1 u2 + D2 u1, with D forward
+    # differences that commute: D2 D2 eps11 + D1 D1 eps22 - 2 D1 D2 eps12 = 0.
+    D1 = lambda f: np.roll(f, -1, axis=1) - f
+    D2 = lambda f: np.roll(f, -1, axis=0) - f
+    inc = D2(D2(e[..., 0, 0])) + D1(D1(e[..., 1, 1])) - 2 * D1(D2(e[..., 0, 1]))
+    assert np.abs(inc).max() < 1e-12
+
+
+def test_continuum_limit():
+    """G(q) -> -Gamma0(q) (Moulinec-Suquet) as q -> 0 (Sec. 2), error O(q)."""
+    errs = []
+    for L in (64, 256, 1024):
+        m = np.array([[1, 0], [1, 1], [2, -1]])
+        q = 2 * np.pi * m / L
+        k = 2 * np.sin(q / 2) * np.exp(0.5j * q)
+        G = dg.green_tensor(k, LAM0, MU0)
+        Gam = dg.continuum_gamma0(q, LAM0, MU0)
+        errs.append(np.abs(G + Gam).max() / np.abs(Gam).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-2
+    assert errs[0] / errs[2] > 10   # at least first-order convergence
+
+
+def test_dg1_is_real():
+    G1 = dg.green_dg1_on_grid(16, LAM0, MU0)
+    assert np.abs(G1.imag).max() < 1e-15
+
+
+def test_fourier_divergence_equals_real_space():
+    """The paper evaluates <|div sigma|^2> in Fourier space; Parseval makes it
+    equal to the real-space backward-difference form."""
+    rng = np.random.default_rng(9)
+    L = 16
+    a = rng.normal(size=(L, L, 3, 3))
+    sig = 0.5 * (a + np.swapaxes(a, -1, -2))
+    real = np.mean(np.sum(alm.divergence(sig) ** 2, axis=-1))
+    four = alm.divergence_fourier(sig)
+    assert abs(real - four) < 1e-12 * real
