@@ -1,0 +1,178 @@
+"""Benchmark: pixel-iterations per second of the discrete-Green augmented-
+Lagrangian solve on one MI355X.
+
+Workload: one realization, L = 4096, Bernoulli voids f = 0.3 (seed 0), matrix
+mu = 1, lambda = 2, Y = 1, reference medium twice the matrix, simple shear
+E = (0, 0, e) ramped over 40 load steps to 4 Y / mu, tolerance 1e-6, FP32
+fields with FP64 norms.  A "step" is one load step of that ramp: the device
+iterates to convergence (or max_iter) from the previous step's state and
+writes sigma, eps and the plastic mask.  Warmup steps are the first load
+steps of the ramp; timed steps follow them.
+
+Output: one JSON line with the throughput, the per-kernel roofline of the
+dominant kernel (HIP event timing on the solver's stream over the timed
+region), the same throughput in FP64, and the CPU oracle timed on a bounded
+sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--L", type=int, default=4096)
+    ap.add_argument("--max-iter", type=int, default=500)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(L: int, fs: int):
+    """Compulsory HBM bytes per launch of the row and column passes.
+
+    Half spectrum: L rows x (L/2 + 1) momenta x 3 complex values.
+    Row pass: read + write the spectrum, read + write eps (4 planes), read mask.
+    Column pass: read + write the spectrum.
+    """
+    spec = L * (L // 2 + 1) * 3 * 2 * fs
+    row = 2 * spec + 2 * 4 * L * L * fs + L * L
+    col = 2 * spec
+    return row, col
+
+
+def run_gpu(L, precision, steps, warmup, max_iter, timing=True):
+    import torch
+
+    from paper_0802_2488_amd import synth
+    from paper_0802_2488_amd import solver as pms
+
+    kind, nsteps = "shear", 40
+    path = synth.load_path(kind, nsteps, synth.default_emax(kind, 1.0, 1.0))
+    assert warmup + steps <= nsteps
+    mask = pms.device_mask(L, 0.3, 0)
+    params = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=1e-6, max_iter=max_iter, precision=precision)
+    s = pms.Solver(mask, params)
+    for n in range(warmup):
+        s.step(path[n])
+    torch.cuda.synchronize()
+    if timing:
+        s.timing(True)
+    t0 = time.perf_counter()
+    recs = []
+    for n in range(warmup, warmup + steps):
+        r = s.step(path[n])
+        recs.append(r)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = s.timing(False) if timing else None
+    s.close()
+    iters = sum(r.iters for r in recs)
+    info = dict(
+        iters_per_step=[r.iters for r in recs],
+        converged=[r.converged for r in recs],
+        res_eq=[r.res_eq for r in recs],
+        res_mac=[r.res_mac for r in recs],
+        res_cmp=[r.res_cmp for r in recs],
+        sigma12_mean=[float(r.sigma_mean[3]) for r in recs],
+        plastic_fraction=[float(r.plastic.float().mean()) for r in recs],
+    )
+    return dict(value=L * L * iters / dt, seconds=dt, iters=iters, info=info, timing=tm)
+
+
+def cpu_baseline(L):
+    """The FP64 oracle on this host: one iteration of the first load step."""
+    import numpy as np
+
+    from oracle import alm
+    from paper_0802_2488_amd import synth
+
+    cores = len(os.sched_getaffinity(0))
+    mask = synth.bernoulli_mask(L, 0.3, 0)
+    E = synth.load_path("shear", 40, 4.0)[0]
+    s = alm.Solver(mask, alm.Params(L=L))
+    s.start(E)
+    n = 1
+    t0 = time.perf_counter()
+    for _ in range(n):
+        s.iterate(E)
+    dt = time.perf_counter() - t0
+    del s
+    return dict(value=L * L * n / dt, unit="pixel-iters/s", cores=1, host_cores=cores, kind="oracle",
+                sample=f"{n} augmented-Lagrangian iteration of load step 1 at L={L} (FP64 numpy, "
+                       f"numpy FFT single-threaded; Green tensor setup excluded), {dt:.1f} s")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(the solve is per-GPU; see the sharding notes in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    L = a.L
+    r32 = run_gpu(L, "fp32", a.steps, a.warmup, a.max_iter)
+    print(f"# fp32 done: {r32['value']:.4e} px-iter/s over {r32['iters']} iterations", file=sys.stderr, flush=True)
+    row_b, col_b = algorithmic_bytes(L, 4)
+    tm = r32["timing"]
+    row_avg_ms = tm["row_ms"] / max(tm["row_launches"], 1)
+    col_avg_ms = tm["col_ms"] / max(tm["col_launches"], 1)
+    row_gbs = row_b / (row_avg_ms * 1e-3) / 1e9
+    col_gbs = col_b / (col_avg_ms * 1e-3) / 1e9
+    r64 = None
+    if not a.no_fp64:
+        r64 = run_gpu(L, "fp64", min(a.steps, 2), 1, min(a.max_iter, 200))
+        print(f"# fp64 done: {r64['value']:.4e} px-iter/s", file=sys.stderr, flush=True)
+    cpu = None if a.no_cpu else cpu_baseline(L)
+    ms_per_step = 1e3 * r32["seconds"] / a.steps
+    out = {
+        "metric": "pixel-iters/s at L=4096 FP32 vs FP64; batched p50/p99 solve latency",
+        "value": r32["value"],
+        "unit": "pixel-iters/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 fields, f64 norms",
+        "data": "synthetic (seeded Bernoulli void mask)",
+        "config": {"workload": f"single realization L={L}, f=0.3, simple shear to 4Y/mu over 40 load steps, "
+                               f"tol 1e-6, FP32 fields + FP64 norms; step = one load step (max_iter "
+                               f"{a.max_iter})",
+                   "L": L, "f": 0.3, "seed": 0, "load_steps_timed": list(range(a.warmup + 1, a.warmup + a.steps + 1)),
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_row (inverse row FFT + pointwise step + forward row FFT)",
+                     "achieved": row_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": row_gbs / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_launch": row_b, "avg_launch_ms": row_avg_ms},
+        "kernels": {
+            "k_column": {"achieved_GBs": col_gbs, "frac": col_gbs / HBM_PEAK_GBS, "avg_launch_ms": col_avg_ms,
+                         "algorithmic_bytes_per_launch": col_b},
+            "reductions_ms_per_iter": tm["other_ms"] / max(tm["iterations"], 1),
+        },
+        "iterations": r32["info"],
+        "fp64": None if r64 is None else {"value": r64["value"], "unit": "pixel-iters/s",
+                                          "iters_per_step": r64["info"]["iters_per_step"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

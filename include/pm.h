@@ -1,0 +1,225 @@
+/*
+ * pm.h - C ABI of the MI355X discrete-Green FFT solver for 2D
+ * elastic-perfectly plastic, pixelwise disordered porous media
+ * (Willot & Pellegrini, arXiv:0802.2488).
+ *
+ * The problem (Sec. 2, first paragraph; eq. 1): an L x L periodic lattice of
+ * pixels, each either a void (stress free) or an elastic-perfectly plastic
+ * Mises matrix element with flow stress Y under deformation theory; strains
+ * are forward differences of a periodic displacement, equilibrium uses
+ * backward differences; an overall strain E is prescribed and increased step
+ * by step (Sec. 2, end of "Discrete Green functions").  The solver is the
+ * augmented-Lagrangian Lippmann-Schwinger FFT iteration (Sec. 1) with the
+ * discrete Green tensor of eq. 3 and the convergence indicators of Sec. 2,
+ * "Convergence issues".
+ *
+ * Conventions of every entry point
+ *   - All functions are extern "C", never throw, and return an int status
+ *     (PM_OK = 0 or a negative PM_E* code).  pm_last_error() then returns a
+ *     thread-local message for the last failing call of the thread.
+ *   - Device pointers are HIP device memory of the current device; host
+ *     pointers are ordinary host memory.  The library never allocates device
+ *     memory: the caller provides the workspace (pm_workspace_bytes) and all
+ *     output buffers, and keeps them alive while they are in use.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work of a solver is issued on its stream.
+ *   - Fields are row-major [x2][x1] with x1 (the direction of e^1) the
+ *     contiguous index, p = x2 * L + x1.  Tensor fields are stored as planes
+ *     of L*L values in the order 11, 22, 33, 12 (tensor components; the
+ *     shear plane holds eps_12, not the engineering strain 2 eps_12).
+ *   - Precision: PM_FP32 keeps fields and FFTs in float and every norm,
+ *     mean and convergence test in double; PM_FP64 is double throughout.
+ *     Output planes use the field precision.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define PM_OK 0
+#define PM_EINVAL (-1)  /* invalid argument: L, moduli, tolerances, pointers, workspace size */
+#define PM_EDEVICE (-3) /* a HIP runtime call failed */
+#define PM_ENOCONV (-4) /* step stopped at max_iter; outputs are written and valid as iterates */
+#define PM_ENAN (-5)    /* a non-finite value reached the FP64 reductions; outputs are written */
+#define PM_EBUSY (-6)   /* batch/serving pool cannot admit the request now */
+
+#define PM_FP32 0
+#define PM_FP64 1
+
+/* Supported grid sizes: L a power of two with 4 <= L <= PM_MAX_L. */
+#define PM_MAX_L 8192
+
+/*
+ * Solver parameters.
+ *   L                grid side, power of two in [4, PM_MAX_L].
+ *   mu, lambda       Lame moduli of the matrix (3-D isotropic; mu > 0,
+ *                    3 lambda + 2 mu > 0).
+ *   Y                flow stress (Mises norm of the stress in plastic zones, Y > 0).
+ *   mu0, lambda0     reference medium of the Green tensor and penalty of the
+ *                    augmented Lagrangian (eq. 3, "reference medium of Lame
+ *                    moduli mu and lambda"); 0 selects twice the matrix moduli.
+ *                    Must satisfy mu0 > 0 and lambda0 + mu0 > 0.
+ *   eta_eq           tolerance on the equilibrium indicator eta_1
+ *                    (<|div sigma|^2>^(1/2) / |<sigma>|), Sec. 2.
+ *   eta_mac          tolerance on eta_2 (change of <sigma> between iterations).
+ *   eta_cmp          tolerance on the augmented-Lagrangian constraint
+ *                    <|e - eps|^2>^(1/2) / |E|.  A step converges at the first
+ *                    iteration >= 2 where all three hold.
+ *   max_iter         iteration cap per load step (>= 1).
+ *   check_every      iterations issued between host polls of the device
+ *                    convergence flag (0 = automatic).  The test itself runs
+ *                    on the device at every iteration, so results do not
+ *                    depend on this value.
+ *   precision        PM_FP32 or PM_FP64.
+ *   green_variant    0: G(q1, q2) of eq. 3; 1: G(-q1, -q2); 2: G(-q1, q2);
+ *                    3: G(q1, -q2) (the four tensors of the DG2 scheme).
+ */
+typedef struct pm_params {
+  int32_t L;
+  double mu, lambda, Y;
+  double mu0, lambda0;
+  double eta_eq, eta_mac, eta_cmp;
+  int32_t max_iter;
+  int32_t check_every;
+  int32_t precision;
+  int32_t green_variant;
+} pm_params;
+
+/*
+ * Per-step outputs.  Device pointers may be NULL to skip that output.
+ *   sigma    device, 4 planes (11, 22, 33, 12): S(eps), exactly 0 on voids.
+ *   eps      device, 4 planes: the pointwise strain of the last iteration
+ *            (eps_33 -> 0 at convergence; arbitrary but finite in voids).
+ *   plastic  device uint8 L*L: 1 on matrix pixels on the capped branch of the
+ *            Mises law (3 mu eps_eq > Y), else 0 (Sec. 3, plastic phase).
+ *   host results: <sigma>, <eps> (11, 22, 33, 12), final indicators,
+ *   iterations of this step, converged flag, and the step status code.
+ */
+typedef struct pm_step_out {
+  void* sigma;
+  void* eps;
+  uint8_t* plastic;
+  double sigma_mean[4];
+  double eps_mean[4];
+  double res_eq, res_mac, res_cmp;
+  int32_t iters;
+  int32_t converged;
+  int32_t status;
+} pm_step_out;
+
+typedef struct pm_solver pm_solver;
+
+/* Human-readable text for a status code (static storage). */
+const char* pm_status_string(int status);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* pm_last_error(void);
+
+/*
+ * Bytes of device workspace a solver with these parameters needs
+ * (strain state, half spectrum, twiddle and momentum tables, FP64 partials,
+ * device convergence state).  Returns 0 if the parameters are invalid.
+ */
+size_t pm_workspace_bytes(const pm_params* params);
+
+/*
+ * Create a solver for one realization.
+ *   out          receives the handle (host memory).
+ *   params       copied; see pm_params.
+ *   d_void_mask  device uint8 L*L, 1 = void (Sec. 2, pixels are voids with
+ *                concentration f), borrowed until pm_solver_destroy.
+ *   d_workspace  device memory of at least pm_workspace_bytes(params),
+ *                256-byte aligned, borrowed until pm_solver_destroy.
+ *   stream       hipStream_t for all work of this solver.
+ * The handle is bound to one stream and is not thread safe.  The first
+ * pm_solver_step starts from eps = E, lambda = S(E) on matrix pixels.
+ * Errors: PM_EINVAL (parameters, NULL pointers, small or misaligned
+ * workspace), PM_EDEVICE.
+ */
+int pm_solver_create(pm_solver** out, const pm_params* params, const uint8_t* d_void_mask, void* d_workspace,
+                     size_t workspace_bytes, void* stream);
+
+/*
+ * One load step at overall strain E = (E11, E22, E12), E33 = 0 (plane
+ * strain), continuing from the state of the previous step (only the mean
+ * strain changes).  Iterates on the device until converged or max_iter,
+ * then writes the requested outputs and fills the host fields of *out.
+ * E = 0 gives the zero solution with iters = 0 and resets the state.
+ * Returns PM_OK on convergence, PM_ENOCONV or PM_ENAN with outputs written,
+ * PM_EINVAL or PM_EDEVICE on errors.  Blocks until the step is done.
+ */
+int pm_solver_step(pm_solver* solver, const double E[3], pm_step_out* out);
+
+/* Release the handle (not the borrowed mask or workspace). */
+int pm_solver_destroy(pm_solver* solver);
+
+/*
+ * Fill dst (device if on_device != 0, else host) with the Bernoulli void
+ * mask of Sec. 2: pixel p = x2 * L + x1 is a void (1) iff
+ * (splitmix64(seed ^ splitmix64(p)) >> 11) * 2^-53 < f, where splitmix64 is
+ * the SplitMix64 output function.  L in [1, 65536]; 0 <= f <= 1.
+ */
+int pm_bernoulli_mask(uint8_t* dst, int32_t L, double f, uint64_t seed, int32_t on_device, void* stream);
+
+/* Complex numbers per row of the internal half spectrum (>= L/2 + 1). */
+int64_t pm_spectrum_pitch(int32_t L);
+
+/*
+ * Kernel-level entry points on a solver's own buffers (used to check each
+ * kernel in isolation).  The half spectrum is L rows of pm_spectrum_pitch(L)
+ * momenta m1 = 0..L/2, each holding three interleaved complex values
+ * (components 11, 22, 12) in the field precision; row index m2 = 0..L-1.
+ *
+ * pm_solver_buffers   device pointers of the strain state (4 planes) and
+ *                     of the half spectrum.
+ * pm_debug_forward    d_real: 3 planes (11, 22, 12).  Spectrum := the 2-D
+ *                     DFT sum_x f(x) exp(-i q.x) of each plane (rows m1 <= L/2).
+ * pm_debug_inverse    d_real := the unnormalised inverse 2-D DFT
+ *                     sum_q F(q) exp(+i q.x) of the Hermitian-extended
+ *                     spectrum (L^2 times numpy.fft.irfft2).
+ * pm_debug_green      spectrum(q) := G(q):spectrum(q) (eq. 3, built from
+ *                     mu0, lambda0, green_variant) for q != 0 and E at q = 0.
+ * All three issue work on the solver's stream and synchronise it.
+ */
+int pm_solver_buffers(pm_solver* solver, void** d_eps, void** d_spectrum);
+
+/*
+ * Per-kernel device time of the iterations a solver has run while timing was
+ * on, from HIP events recorded on the solver's stream around each launch.
+ *   col_ms / col_launches      column pass (FFT, Green tensor, inverse FFT)
+ *   row_ms / row_launches      row pass (inverse FFT, pointwise step, FFT)
+ *   other_ms                   reductions and equilibrium residual
+ * Only iterations that did work are counted (launches after convergence
+ * exit at once and are excluded).
+ */
+typedef struct pm_kernel_timing {
+  double col_ms;
+  int64_t col_launches;
+  double row_ms;
+  int64_t row_launches;
+  double other_ms;
+  int64_t iterations;
+} pm_kernel_timing;
+
+/*
+ * enable = 1 resets the totals and starts timing; 0 stops it.  While timing
+ * is on the host waits for each group of check_every iterations before
+ * issuing the next (no overlap of host polling with device work).  out (may
+ * be NULL) receives the totals accumulated so far.
+ */
+int pm_solver_timing(pm_solver* solver, int32_t enable, pm_kernel_timing* out);
+int pm_debug_forward(pm_solver* solver, const void* d_real);
+int pm_debug_inverse(pm_solver* solver, void* d_real);
+int pm_debug_green(pm_solver* solver, const double E[3]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM_H */

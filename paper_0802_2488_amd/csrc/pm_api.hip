@@ -1,0 +1,506 @@
+// C-ABI layer: parameter checks, workspace layout, tables, and the host loop
+// of one load step.  All arithmetic of the method runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pm.h"
+#include "pm_internal.h"
+
+using pm::DevParams;
+using pm::DevState;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define PM_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(PM_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t eps, spec, tw, ktab, part, part2, state, total;
+  long pitch;
+  int nrow, ndiv;
+};
+
+// Resolve defaults and validate; fills *q.
+int check_params(const pm_params* p, pm_params* q) {
+  if (!p) return fail(PM_EINVAL, "params is NULL");
+  *q = *p;
+  if (!is_pow2(q->L) || q->L < 4 || q->L > PM_MAX_L)
+    return fail(PM_EINVAL, "L = %d must be a power of two in [4, %d]", q->L, PM_MAX_L);
+  if (!(q->mu > 0) || !(3 * q->lambda + 2 * q->mu > 0) || !(q->Y > 0) || !std::isfinite(q->lambda) ||
+      !std::isfinite(q->mu) || !std::isfinite(q->Y))
+    return fail(PM_EINVAL, "need mu > 0, 3 lambda + 2 mu > 0, Y > 0 (got mu=%g lambda=%g Y=%g)", q->mu, q->lambda,
+                q->Y);
+  if (q->mu0 == 0.0) q->mu0 = 2.0 * q->mu;
+  if (q->lambda0 == 0.0) q->lambda0 = 2.0 * q->lambda;
+  if (!(q->mu0 > 0) || !(q->lambda0 + q->mu0 > 0) || !std::isfinite(q->lambda0))
+    return fail(PM_EINVAL, "reference medium needs mu0 > 0 and lambda0 + mu0 > 0");
+  if (!(q->eta_eq >= 0) || !(q->eta_mac >= 0) || !(q->eta_cmp >= 0))
+    return fail(PM_EINVAL, "tolerances must be >= 0");
+  if (q->max_iter < 1) return fail(PM_EINVAL, "max_iter must be >= 1");
+  if (q->check_every < 0) return fail(PM_EINVAL, "check_every must be >= 0");
+  if (q->precision != PM_FP32 && q->precision != PM_FP64) return fail(PM_EINVAL, "precision must be PM_FP32 or PM_FP64");
+  if (q->green_variant < 0 || q->green_variant > 3) return fail(PM_EINVAL, "green_variant must be 0..3");
+  return PM_OK;
+}
+
+Layout make_layout(const pm_params& q) {
+  Layout lo{};
+  const size_t L = (size_t)q.L;
+  const size_t fs = q.precision == PM_FP64 ? 8 : 4;
+  lo.pitch = pm_spectrum_pitch(q.L);
+  lo.nrow = q.precision == PM_FP64 ? pm::row_grid<double>(q.L) : pm::row_grid<float>(q.L);
+  lo.ndiv = pm::div_grid(q.L);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  lo.eps = take(4 * L * L * fs);
+  lo.spec = take(L * (size_t)lo.pitch * 3 * 2 * fs);
+  lo.tw = take(L * 2 * fs);
+  lo.ktab = take(L * 2 * fs);
+  lo.part = take((size_t)lo.nrow * pm::NPART * sizeof(double));
+  lo.part2 = take((size_t)lo.ndiv * sizeof(double));
+  lo.state = take(sizeof(DevState));
+  lo.total = off;
+  return lo;
+}
+
+}  // namespace
+
+struct pm_solver {
+  pm_params p;
+  DevParams prm;
+  Layout lo;
+  hipStream_t stream;
+  int device;
+  const uint8_t* mask;
+  char* ws;
+  void* eps;
+  void* spec;
+  void* tw;
+  void* ktab;
+  double* part;
+  double* part2;
+  DevState* st;
+  DevState* hst;   // pinned host copies (two slots)
+  hipEvent_t ev[2];
+  bool started;
+  int chunk;
+  // opt-in per-kernel timing
+  bool timing;
+  std::vector<hipEvent_t> tev;   // 4 events per iteration of one chunk
+  pm_kernel_timing tacc;
+};
+
+namespace {
+
+template <typename T>
+int upload_tables(pm_solver* s) {
+  const int L = s->p.L;
+  std::vector<pm::cx<T>> tw(L), kt(L);
+  for (int i = 0; i < L; ++i) {
+    // exp(-2 pi i i / L), and k(m) = 2 sin(q/2) exp(i q/2) = sin q + i 2 sin^2(q/2)
+    const double a = 2.0 * M_PI * (double)i / (double)L;
+    tw[i].re = (T)std::cos(a);
+    tw[i].im = (T)(-std::sin(a));
+    const double h = std::sin(0.5 * a);
+    kt[i].re = (T)std::sin(a);
+    kt[i].im = (T)(2.0 * h * h);
+  }
+  PM_HIP(hipMemcpyAsync(s->tw, tw.data(), L * sizeof(pm::cx<T>), hipMemcpyHostToDevice, s->stream));
+  PM_HIP(hipMemcpyAsync(s->ktab, kt.data(), L * sizeof(pm::cx<T>), hipMemcpyHostToDevice, s->stream));
+  PM_HIP(hipStreamSynchronize(s->stream));
+  return PM_OK;
+}
+
+template <typename T>
+pm::RowArgs<T> row_args(pm_solver* s, int mode, const double* E, bool with_state) {
+  pm::RowArgs<T> a{};
+  a.spec = (pm::cx<T>*)s->spec;
+  a.tw = (const pm::cx<T>*)s->tw;
+  a.eps = (T*)s->eps;
+  a.mask = s->mask;
+  a.partials = s->part;
+  a.state = with_state ? s->st : nullptr;
+  a.pitch = s->lo.pitch;
+  a.mode = mode;
+  for (int i = 0; i < 3; ++i) a.E[i] = E ? E[i] : 0.0;
+  a.prm = s->prm;
+  return a;
+}
+
+template <typename T>
+pm::ColArgs<T> col_args(pm_solver* s, int mode, double scale, const double* E, bool with_state) {
+  pm::ColArgs<T> a{};
+  a.spec = (pm::cx<T>*)s->spec;
+  a.tw = (const pm::cx<T>*)s->tw;
+  a.ktab = (const pm::cx<T>*)s->ktab;
+  a.state = with_state ? s->st : nullptr;
+  a.pitch = s->lo.pitch;
+  a.mode = mode;
+  const int v = s->p.green_variant;
+  a.flip1 = (v == 1 || v == 2) ? 1 : 0;
+  a.flip2 = (v == 1 || v == 3) ? 1 : 0;
+  a.lam0 = s->p.lambda0;
+  a.mu0 = s->p.mu0;
+  a.scale = scale;
+  for (int i = 0; i < 3; ++i) a.E[i] = E ? E[i] : 0.0;
+  return a;
+}
+
+template <typename T>
+int iterate_once(pm_solver* s, int slot_in_chunk) {
+  const int L = s->p.L;
+  const double sc = 1.0 / ((double)L * (double)L);
+  hipEvent_t* ev = s->timing ? &s->tev[4 * slot_in_chunk] : nullptr;
+  if (ev) PM_HIP(hipEventRecord(ev[0], s->stream));
+  PM_HIP(pm::launch_col<T>(L, col_args<T>(s, pm::COL_ALL, sc, nullptr, true), s->stream));
+  if (ev) PM_HIP(hipEventRecord(ev[1], s->stream));
+  PM_HIP(pm::launch_row<T>(L, row_args<T>(s, pm::ROW_ITER, nullptr, true), s->stream));
+  if (ev) PM_HIP(hipEventRecord(ev[2], s->stream));
+  PM_HIP(pm::launch_reduce(s->part, s->lo.nrow, s->st, s->prm, s->stream));
+  PM_HIP(pm::launch_div<T>((const T*)s->eps, s->mask, s->part2, s->st, s->prm, L, 0, s->stream));
+  if (ev) PM_HIP(hipEventRecord(ev[3], s->stream));
+  return PM_OK;
+}
+
+// Add the event times of the first `executed` iterations of a finished chunk.
+int collect_timing(pm_solver* s, int executed) {
+  for (int i = 0; i < executed; ++i) {
+    float a = 0.f, b = 0.f, c = 0.f;
+    PM_HIP(hipEventElapsedTime(&a, s->tev[4 * i], s->tev[4 * i + 1]));
+    PM_HIP(hipEventElapsedTime(&b, s->tev[4 * i + 1], s->tev[4 * i + 2]));
+    PM_HIP(hipEventElapsedTime(&c, s->tev[4 * i + 2], s->tev[4 * i + 3]));
+    s->tacc.col_ms += a;
+    s->tacc.row_ms += b;
+    s->tacc.other_ms += c;
+    s->tacc.col_launches += 1;
+    s->tacc.row_launches += 1;
+    s->tacc.iterations += 1;
+  }
+  return PM_OK;
+}
+
+template <typename T>
+int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
+  const int L = s->p.L;
+  const double nE = std::sqrt(E[0] * E[0] + E[1] * E[1] + 2.0 * E[2] * E[2]);
+  if (!std::isfinite(nE)) return fail(PM_EINVAL, "E is not finite");
+  if (nE == 0.0) {
+    // Zero load: the zero field is the solution; reset the state to it.
+    const double z[3] = {0.0, 0.0, 0.0};
+    PM_HIP(pm::launch_row<T>(L, row_args<T>(s, pm::ROW_INIT, z, false), s->stream));
+    s->started = true;
+    if (out && (out->sigma || out->eps || out->plastic))
+      PM_HIP(pm::launch_emit<T>((const T*)s->eps, s->mask, (T*)out->sigma, (T*)out->eps, out->plastic, s->prm, L,
+                                s->stream));
+    PM_HIP(hipStreamSynchronize(s->stream));
+    if (out) {
+      for (int i = 0; i < 4; ++i) out->sigma_mean[i] = out->eps_mean[i] = 0.0;
+      out->res_eq = out->res_mac = out->res_cmp = 0.0;
+      out->iters = 0;
+      out->converged = 1;
+      out->status = PM_OK;
+    }
+    return PM_OK;
+  }
+  if (!s->started) {
+    PM_HIP(pm::launch_row<T>(L, row_args<T>(s, pm::ROW_INIT, E, false), s->stream));
+    s->started = true;
+  }
+  PM_HIP(pm::launch_begin(s->st, E, 1e-12 * s->p.mu * nE, s->stream));
+  const int max_iter = s->p.max_iter;
+  int issued = 0, slot = 0, pend = -1, fin = -1;
+  while (fin < 0 && s->timing) {
+    // timed mode: one chunk at a time so each chunk's executed iterations are known
+    const int n = std::min(s->chunk, max_iter - issued);
+    for (int i = 0; i < n; ++i) {
+      int rc = iterate_once<T>(s, i);
+      if (rc != PM_OK) return rc;
+    }
+    const int before = issued == 0 ? 0 : s->hst[0].iter;
+    issued += n;
+    PM_HIP(hipMemcpyAsync(&s->hst[0], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+    PM_HIP(hipStreamSynchronize(s->stream));
+    int rc = collect_timing(s, std::min(n, s->hst[0].iter - before));
+    if (rc != PM_OK) return rc;
+    if (s->hst[0].halted || issued >= max_iter) fin = 0;
+  }
+  while (fin < 0) {
+    if (issued < max_iter) {
+      const int n = std::min(s->chunk, max_iter - issued);
+      for (int i = 0; i < n; ++i) {
+        int rc = iterate_once<T>(s, i);
+        if (rc != PM_OK) return rc;
+      }
+      issued += n;
+      PM_HIP(hipMemcpyAsync(&s->hst[slot], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+      PM_HIP(hipEventRecord(s->ev[slot], s->stream));
+      const int prev = pend;
+      pend = slot;
+      slot ^= 1;
+      if (prev >= 0) {
+        PM_HIP(hipEventSynchronize(s->ev[prev]));
+        if (s->hst[prev].halted) fin = prev;
+      }
+    } else {
+      PM_HIP(hipEventSynchronize(s->ev[pend]));
+      fin = pend;
+    }
+  }
+  DevState hs = s->hst[fin];
+  if (!hs.halted) return fail(PM_EDEVICE, "device did not halt after max_iter iterations");
+  if (hs.status != pm::ST_CONVERGED) {
+    // report the equilibrium indicator of the final iterate
+    PM_HIP(pm::launch_div<T>((const T*)s->eps, s->mask, s->part2, s->st, s->prm, L, 1, s->stream));
+    PM_HIP(hipMemcpyAsync(&s->hst[0], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+    PM_HIP(hipStreamSynchronize(s->stream));
+    hs.res_eq = s->hst[0].res_eq;
+  }
+  if (out && (out->sigma || out->eps || out->plastic))
+    PM_HIP(pm::launch_emit<T>((const T*)s->eps, s->mask, (T*)out->sigma, (T*)out->eps, out->plastic, s->prm, L,
+                              s->stream));
+  PM_HIP(hipStreamSynchronize(s->stream));
+  int rc = PM_OK;
+  if (hs.status == pm::ST_NOCONV) rc = PM_ENOCONV;
+  if (hs.status == pm::ST_NAN) rc = PM_ENAN;
+  if (out) {
+    for (int i = 0; i < 4; ++i) {
+      out->sigma_mean[i] = hs.sm[i];
+      out->eps_mean[i] = hs.em[i];
+    }
+    out->res_eq = hs.res_eq;
+    out->res_mac = hs.res_mac;
+    out->res_cmp = hs.res_cmp;
+    out->iters = hs.iter;
+    out->converged = hs.status == pm::ST_CONVERGED ? 1 : 0;
+    out->status = rc;
+  }
+  if (rc == PM_ENOCONV) fail(rc, "load step stopped at max_iter = %d", max_iter);
+  if (rc == PM_ENAN) fail(rc, "non-finite value in the reductions at iteration %d", hs.iter);
+  return rc;
+}
+
+}  // namespace
+
+namespace {
+template <typename T>
+int debug_forward(pm_solver* s, const void* d_real) {
+  auto ra = row_args<T>(s, pm::ROW_FWD, nullptr, false);
+  ra.real_in = (const T*)d_real;
+  PM_HIP(pm::launch_row<T>(s->p.L, ra, s->stream));
+  PM_HIP(pm::launch_col<T>(s->p.L, col_args<T>(s, pm::COL_FWD, 1.0, nullptr, false), s->stream));
+  PM_HIP(hipStreamSynchronize(s->stream));
+  return PM_OK;
+}
+template <typename T>
+int debug_inverse(pm_solver* s, void* d_real) {
+  PM_HIP(pm::launch_col<T>(s->p.L, col_args<T>(s, pm::COL_INV, 1.0, nullptr, false), s->stream));
+  auto ra = row_args<T>(s, pm::ROW_INV, nullptr, false);
+  ra.real_out = (T*)d_real;
+  PM_HIP(pm::launch_row<T>(s->p.L, ra, s->stream));
+  PM_HIP(hipStreamSynchronize(s->stream));
+  return PM_OK;
+}
+template <typename T>
+int debug_green(pm_solver* s, const double* E) {
+  PM_HIP(pm::launch_col<T>(s->p.L, col_args<T>(s, pm::COL_GREEN, 1.0, E, false), s->stream));
+  PM_HIP(hipStreamSynchronize(s->stream));
+  return PM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char* pm_status_string(int status) {
+  switch (status) {
+    case PM_OK: return "ok";
+    case PM_EINVAL: return "invalid argument";
+    case PM_EDEVICE: return "HIP device error";
+    case PM_ENOCONV: return "not converged within max_iter";
+    case PM_ENAN: return "non-finite value";
+    case PM_EBUSY: return "busy: cannot admit now";
+    default: return "unknown status";
+  }
+}
+
+const char* pm_last_error(void) { return g_err.c_str(); }
+
+int64_t pm_spectrum_pitch(int32_t L) { return ((int64_t)(L / 2 + 1) + 15) / 16 * 16; }
+
+size_t pm_workspace_bytes(const pm_params* params) {
+  pm_params q;
+  if (check_params(params, &q) != PM_OK) return 0;
+  return make_layout(q).total;
+}
+
+int pm_solver_create(pm_solver** out, const pm_params* params, const uint8_t* d_void_mask, void* d_workspace,
+                     size_t workspace_bytes, void* stream) {
+  if (!out) return fail(PM_EINVAL, "out is NULL");
+  *out = nullptr;
+  pm_params q;
+  int rc = check_params(params, &q);
+  if (rc != PM_OK) return rc;
+  if (!d_void_mask || !d_workspace) return fail(PM_EINVAL, "mask and workspace must be device pointers");
+  if (((uintptr_t)d_workspace) % 256 != 0) return fail(PM_EINVAL, "workspace must be 256-byte aligned");
+  Layout lo = make_layout(q);
+  if (workspace_bytes < lo.total)
+    return fail(PM_EINVAL, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, lo.total);
+  pm_solver* s = new (std::nothrow) pm_solver();
+  if (!s) return fail(PM_EDEVICE, "host allocation failed");
+  s->p = q;
+  s->lo = lo;
+  s->stream = (hipStream_t)stream;
+  s->mask = d_void_mask;
+  s->ws = (char*)d_workspace;
+  s->eps = s->ws + lo.eps;
+  s->spec = s->ws + lo.spec;
+  s->tw = s->ws + lo.tw;
+  s->ktab = s->ws + lo.ktab;
+  s->part = (double*)(s->ws + lo.part);
+  s->part2 = (double*)(s->ws + lo.part2);
+  s->st = (DevState*)(s->ws + lo.state);
+  s->started = false;
+  const long L2 = (long)q.L * q.L;
+  s->chunk = q.check_every > 0 ? q.check_every
+                               : (int)std::max(8L, std::min(128L, (long)(1L << 27) / L2));
+  DevParams& d = s->prm;
+  d.mu = q.mu; d.lam = q.lambda; d.Y = q.Y; d.mu0 = q.mu0; d.lam0 = q.lambda0;
+  d.K = q.lambda + 2.0 * q.mu / 3.0;
+  d.K0 = q.lambda0 + 2.0 * q.mu0 / 3.0;
+  d.sy = std::sqrt(2.0 / 3.0) * q.Y;
+  d.thr_rho = std::sqrt(2.0 / 3.0) * q.Y * (q.mu + q.mu0) / q.mu;
+  d.npx = (double)L2;
+  d.eta_eq = q.eta_eq; d.eta_mac = q.eta_mac; d.eta_cmp = q.eta_cmp;
+  d.max_iter = q.max_iter;
+  d.L = q.L;
+  auto cleanup = [&](int code) {
+    if (s->hst) (void)hipHostFree(s->hst);
+    for (int i = 0; i < 2; ++i)
+      if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
+    delete s;
+    return code;
+  };
+  if (hipGetDevice(&s->device) != hipSuccess) return cleanup(fail(PM_EDEVICE, "hipGetDevice failed"));
+  if (hipHostMalloc((void**)&s->hst, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(PM_EDEVICE, "pinned host allocation failed"));
+  memset(s->hst, 0, 2 * sizeof(DevState));
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming) != hipSuccess)
+      return cleanup(fail(PM_EDEVICE, "hipEventCreate failed"));
+  if (hipMemsetAsync(s->st, 0, sizeof(DevState), s->stream) != hipSuccess)
+    return cleanup(fail(PM_EDEVICE, "hipMemsetAsync failed"));
+  rc = q.precision == PM_FP64 ? upload_tables<double>(s) : upload_tables<float>(s);
+  if (rc != PM_OK) return cleanup(rc);
+  *out = s;
+  return PM_OK;
+}
+
+int pm_solver_step(pm_solver* s, const double E[3], pm_step_out* out) {
+  if (!s || !E) return fail(PM_EINVAL, "solver and E must not be NULL");
+  if (hipSetDevice(s->device) != hipSuccess) return fail(PM_EDEVICE, "hipSetDevice failed");
+  return s->p.precision == PM_FP64 ? step_impl<double>(s, E, out) : step_impl<float>(s, E, out);
+}
+
+int pm_solver_destroy(pm_solver* s) {
+  if (!s) return PM_OK;
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& e : s->tev)
+    if (e) (void)hipEventDestroy(e);
+  if (s->hst) (void)hipHostFree(s->hst);
+  for (int i = 0; i < 2; ++i)
+    if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
+  delete s;
+  return PM_OK;
+}
+
+int pm_solver_timing(pm_solver* s, int32_t enable, pm_kernel_timing* out) {
+  if (!s) return fail(PM_EINVAL, "solver is NULL");
+  if (enable) {
+    if (s->tev.empty()) {
+      s->tev.resize(4 * (size_t)s->chunk, nullptr);
+      for (auto& e : s->tev) PM_HIP(hipEventCreate(&e));
+    }
+    s->tacc = pm_kernel_timing{};
+    s->timing = true;
+  } else {
+    s->timing = false;
+  }
+  if (out) *out = s->tacc;
+  return PM_OK;
+}
+
+int pm_solver_buffers(pm_solver* s, void** d_eps, void** d_spectrum) {
+  if (!s) return fail(PM_EINVAL, "solver is NULL");
+  if (d_eps) *d_eps = s->eps;
+  if (d_spectrum) *d_spectrum = s->spec;
+  return PM_OK;
+}
+
+
+int pm_debug_forward(pm_solver* s, const void* d_real) {
+  if (!s || !d_real) return fail(PM_EINVAL, "NULL argument");
+  return s->p.precision == PM_FP64 ? debug_forward<double>(s, d_real) : debug_forward<float>(s, d_real);
+}
+int pm_debug_inverse(pm_solver* s, void* d_real) {
+  if (!s || !d_real) return fail(PM_EINVAL, "NULL argument");
+  return s->p.precision == PM_FP64 ? debug_inverse<double>(s, d_real) : debug_inverse<float>(s, d_real);
+}
+int pm_debug_green(pm_solver* s, const double E[3]) {
+  if (!s || !E) return fail(PM_EINVAL, "NULL argument");
+  return s->p.precision == PM_FP64 ? debug_green<double>(s, E) : debug_green<float>(s, E);
+}
+
+static uint64_t host_splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int pm_bernoulli_mask(uint8_t* dst, int32_t L, double f, uint64_t seed, int32_t on_device, void* stream) {
+  if (!dst) return fail(PM_EINVAL, "dst is NULL");
+  if (L < 1 || L > 65536) return fail(PM_EINVAL, "L = %d out of range", L);
+  if (!(f >= 0.0 && f <= 1.0)) return fail(PM_EINVAL, "f = %g must be in [0, 1]", f);
+  const long npx = (long)L * L;
+  if (on_device) {
+    PM_HIP(pm::launch_mask(dst, npx, f, seed, (hipStream_t)stream));
+    PM_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return PM_OK;
+  }
+  for (long p = 0; p < npx; ++p) {
+    const uint64_t z = host_splitmix64(seed ^ host_splitmix64((uint64_t)p));
+    dst[p] = ((double)(z >> 11) * 0x1.0p-53) < f ? 1 : 0;
+  }
+  return PM_OK;
+}
+
+}  // extern "C"

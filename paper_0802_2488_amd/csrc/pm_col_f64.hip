@@ -1,0 +1,6 @@
+// Column-pass instantiations, double fields.
+#include "pm_kernels.hpp"
+
+namespace pm {
+template hipError_t launch_col<double>(int, const ColArgs<double>&, hipStream_t);
+}  // namespace pm

@@ -1,0 +1,277 @@
+// Register/LDS radix FFT building blocks for CDNA4 (gfx950, wave64).
+//
+// One transform of length N is carried out by a team of TPF = N / RMAX
+// threads.  Between kernels' compute phases the data sits in registers in the
+// "pattern A" layout: thread t of the team holds elements t + TPF * s,
+// s = 0..RMAX-1, in register slot s.  The Stockham autosort decomposition
+// (radix RMAX, a smaller middle radix when N is not a power of RMAX, radix
+// RMAX last) both starts from and ends in pattern A, in natural order, so a
+// kernel can
+//   load pattern A from HBM -> FFT -> pointwise work -> FFT -> store
+// with LDS used only for the exchanges between radix stages.
+//
+// Conventions: forward transform DIR = -1, X[k] = sum_n x[n] exp(-2 pi i nk/N);
+// inverse DIR = +1, unnormalised.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pm {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+// multiply by DIR * i
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_diri(cx<T> a) {
+  if constexpr (DIR < 0) return {a.im, -a.re};
+  else return {-a.im, a.re};
+}
+
+// cos(2 pi m / 16) and sin(2 pi m / 16), m = 0..15 (exact mathematical values).
+constexpr double kC16[16] = {
+    1.0, 0.923879532511286756128183189396788933, 0.707106781186547524400844362104849039,
+    0.382683432365089771728459984030398866, 0.0, -0.382683432365089771728459984030398866,
+    -0.707106781186547524400844362104849039, -0.923879532511286756128183189396788933, -1.0,
+    -0.923879532511286756128183189396788933, -0.707106781186547524400844362104849039,
+    -0.382683432365089771728459984030398866, 0.0, 0.382683432365089771728459984030398866,
+    0.707106781186547524400844362104849039, 0.923879532511286756128183189396788933};
+constexpr double kS16[16] = {
+    0.0, 0.382683432365089771728459984030398866, 0.707106781186547524400844362104849039,
+    0.923879532511286756128183189396788933, 1.0, 0.923879532511286756128183189396788933,
+    0.707106781186547524400844362104849039, 0.382683432365089771728459984030398866, 0.0,
+    -0.382683432365089771728459984030398866, -0.707106781186547524400844362104849039,
+    -0.923879532511286756128183189396788933, -1.0, -0.923879532511286756128183189396788933,
+    -0.707106781186547524400844362104849039, -0.382683432365089771728459984030398866};
+
+// a * exp(DIR * 2 pi i m / R) for a compile-time m, R in {2, 4, 8, 16}.
+template <int DIR, int R, int M, typename T>
+__device__ __forceinline__ cx<T> twc(cx<T> a) {
+  constexpr int m16 = ((M * (16 / R)) % 16 + 16) % 16;
+  if constexpr (m16 == 0) return a;
+  else if constexpr (m16 == 8) return {-a.re, -a.im};
+  else if constexpr (m16 == 4) return mul_diri<DIR>(a);
+  else if constexpr (m16 == 12) return mul_diri<-DIR>(a);
+  else {
+    constexpr double cd = kC16[m16];
+    constexpr double sd = DIR * kS16[m16];
+    const T c = (T)cd;
+    const T s = (T)sd;
+    return {a.re * c - a.im * s, a.re * s + a.im * c};
+  }
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cx<T>* v) {
+  cx<T> a0 = v[0] + v[2], a1 = v[0] - v[2];
+  cx<T> a2 = v[1] + v[3], a3 = mul_diri<DIR>(v[1] - v[3]);
+  v[0] = a0 + a2;
+  v[2] = a0 - a2;
+  v[1] = a1 + a3;
+  v[3] = a1 - a3;
+}
+
+// Two-level split R = R1 * R2: n = R2 n1 + n2, k = k1 + R1 k2.
+template <int DIR, int R1, int R2, typename T>
+__device__ __forceinline__ void dft_split(cx<T>* v);
+
+template <int DIR, int R, typename T>
+__device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v);
+  else if constexpr (R == 8) dft_split<DIR, 2, 4>(v);
+  else if constexpr (R == 16) dft_split<DIR, 4, 4>(v);
+  else static_assert(R == 2 || R == 4 || R == 8 || R == 16, "unsupported radix");
+}
+
+template <int DIR, int R1, int R2, int N2, int K1, typename T>
+__device__ __forceinline__ void split_tw(cx<T> (&y)[R2][R1]) {
+  y[N2][K1] = twc<DIR, R1 * R2, N2 * K1>(y[N2][K1]);
+  if constexpr (K1 + 1 < R1) split_tw<DIR, R1, R2, N2, K1 + 1>(y);
+  else if constexpr (N2 + 1 < R2) split_tw<DIR, R1, R2, N2 + 1, 0>(y);
+}
+
+template <int DIR, int R1, int R2, typename T>
+__device__ __forceinline__ void dft_split(cx<T>* v) {
+  cx<T> y[R2][R1];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) y[n2][n1] = v[R2 * n1 + n2];
+    dft<DIR, R1>(y[n2]);
+  }
+  split_tw<DIR, R1, R2, 0, 0>(y);
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cx<T> z[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) z[n2] = y[n2][k1];
+    dft<DIR, R2>(z);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = z[k2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Radix plan: N = RMAX^s * rem (rem < RMAX); stages RMAX, ..., rem, RMAX.
+template <int N, int RMAX>
+struct Plan {
+  static constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
+  static constexpr int LN = log2i(N);
+  static constexpr int LR = log2i(RMAX);
+  static constexpr int NFULL = LN / LR;           // number of radix-RMAX stages
+  static constexpr int REM = 1 << (LN - NFULL * LR);
+  static constexpr int NSTAGE = NFULL + (REM > 1 ? 1 : 0);
+  static constexpr int TPF = N / RMAX;
+  static_assert((1 << LN) == N, "N must be a power of two");
+  static_assert(N >= RMAX, "N must be at least RMAX");
+  // radix of stage i: the middle factor sits just before the last stage
+  static constexpr int radix(int i) {
+    return (REM > 1 && NSTAGE >= 2 && i == NSTAGE - 2) ? REM : (REM > 1 && NSTAGE == 1 ? REM : RMAX);
+  }
+  static constexpr int ns(int i) { return i == 0 ? 1 : ns(i - 1) * radix(i - 1); }
+};
+
+// LDS index with one padding word every 16 words (breaks power-of-two strides).
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+template <int N>
+struct LdsSize {
+  static constexpr int value = N + N / 16;
+};
+
+// Twiddle exp(DIR * 2 pi i * idx / N) from a forward table tw[i] = exp(-2 pi i i / N).
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> twl(const cx<T>* __restrict__ tw, int idx) {
+  cx<T> w = tw[idx];
+  if constexpr (DIR > 0) w.im = -w.im;
+  return w;
+}
+
+// Multiply u[1..R-1] by w^r, w = exp(DIR 2 pi i base / N); the powers 1, 2, 4, 8
+// come from the table, the others from at most three products.
+template <int DIR, int R, typename T>
+__device__ __forceinline__ void apply_tw(cx<T>* u, const cx<T>* __restrict__ tw, int base) {
+  if constexpr (R == 2) {
+    u[1] = cmul(u[1], twl<DIR>(tw, base));
+  } else if constexpr (R == 4) {
+    cx<T> w1 = twl<DIR>(tw, base), w2 = twl<DIR>(tw, 2 * base);
+    cx<T> w3 = cmul(w1, w2);
+    u[1] = cmul(u[1], w1);
+    u[2] = cmul(u[2], w2);
+    u[3] = cmul(u[3], w3);
+  } else {
+    cx<T> w[R];
+    w[1] = twl<DIR>(tw, base);
+    w[2] = twl<DIR>(tw, 2 * base);
+    w[4] = twl<DIR>(tw, 4 * base);
+    w[3] = cmul(w[1], w[2]);
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+    if constexpr (R == 16) {
+      w[8] = twl<DIR>(tw, 8 * base);
+#pragma unroll
+      for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) u[r] = cmul(u[r], w[r]);
+  }
+}
+
+// One Stockham stage.  Input: stage 0 takes pattern A from v; later stages
+// read LDS.  Output: the last stage writes pattern A to v; earlier stages
+// write LDS.  Barriers are placed so one LDS buffer can be reused.
+template <int DIR, typename T, int N, int RMAX, int STAGE>
+__device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__ lre, T* __restrict__ lim,
+                                               int t, const cx<T>* __restrict__ tw) {
+  using P = Plan<N, RMAX>;
+  constexpr int R = P::radix(STAGE);
+  constexpr int NS = P::ns(STAGE);
+  constexpr int TPF = P::TPF;
+  constexpr int B = RMAX / R;
+  constexpr bool FIRST = STAGE == 0;
+  constexpr bool LAST = STAGE == P::NSTAGE - 1;
+  cx<T> u[RMAX];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if constexpr (FIRST) {
+        u[b * R + r] = v[b + B * r];
+      } else {
+        const int j = t + b * TPF;
+        const int idx = lpad(j + r * (N / R));
+        u[b * R + r] = {lre[idx], lim[idx]};
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = t + b * TPF;
+    if constexpr (NS > 1) {
+      const int k = j % NS;
+      apply_tw<DIR, R>(&u[b * R], tw, k * (N / (NS * R)));
+    }
+    dft<DIR, R>(&u[b * R]);
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + B * r] = u[b * R + r];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + b * TPF;
+      const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = lpad(base + r * NS);
+        lre[idx] = u[b * R + r].re;
+        lim[idx] = u[b * R + r].im;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int DIR, typename T, int N, int RMAX, int STAGE = 0>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[RMAX], T* lre, T* lim, int t, const cx<T>* tw) {
+  stockham_stage<DIR, T, N, RMAX, STAGE>(v, lre, lim, t, tw);
+  if constexpr (STAGE + 1 < Plan<N, RMAX>::NSTAGE) fft_stages<DIR, T, N, RMAX, STAGE + 1>(v, lre, lim, t, tw);
+}
+
+// Length-N transform of one signal held in pattern A by a team of Plan::TPF
+// threads; every thread of the block must call it (it contains barriers).
+template <int DIR, typename T, int N, int RMAX>
+__device__ __forceinline__ void fft(cx<T> (&v)[RMAX], T* lre, T* lim, int t, const cx<T>* tw) {
+  // An opaque copy of the table pointer per transform keeps the compiler from
+  // holding one transform's twiddles live across unrelated work.
+  const cx<T>* twp = tw;
+  asm volatile("" : "+s"(twp));
+  fft_stages<DIR, T, N, RMAX, 0>(v, lre, lim, t, twp);
+}
+
+}  // namespace pm

@@ -1,0 +1,7 @@
+// Row-pass instantiations, double fields.
+#include "pm_kernels.hpp"
+
+namespace pm {
+template hipError_t launch_row<double>(int, const RowArgs<double>&, hipStream_t);
+template int row_grid<double>(int);
+}  // namespace pm

@@ -1,0 +1,258 @@
+"""GPU parity: every kernel and the whole solve against the FP64 CPU oracle.
+
+All calls go through the C ABI (libpm.so).  Tolerances:
+  FP64 fields: relative L2 stress error <= 1e-10 (iteration locked);
+  FP32 fields: relative L2 stress error <= 1e-4;
+  integer work (masks): bit exact; plastic mask: exact outside the band
+  |trial Mises - Y| <= 1e-5 Y where the branch is decided by rounding.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import alm, dg, hencky  # noqa: E402
+from paper_0802_2488_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0802_2488_amd import solver as pms  # noqa: E402
+
+
+def to_tensor33(planes):
+    """(4, L, L) planes 11, 22, 33, 12 -> (L, L, 3, 3)."""
+    p = planes.detach().cpu().double().numpy()
+    return alm.from_voigt4(np.moveaxis(p, 0, -1))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def oracle_params(L, c0=2.0, Y=1.0, tol=1e-8, max_iter=50000, variant=0):
+    return alm.Params(L=L, mu=1.0, lam=2.0, Y=Y, mu0=c0 * 1.0, lam0=c0 * 2.0, eta_eq=tol, eta_mac=tol,
+                      eta_cmp=tol, max_iter=max_iter, green_variant=variant)
+
+
+def gpu_params(L, precision, c0=2.0, Y=1.0, tol=1e-8, max_iter=50000, variant=0, check_every=0):
+    return pms.make_params(L, mu=1.0, lam=2.0, Y=Y, mu0=c0 * 1.0, lam0=c0 * 2.0, tol=tol, max_iter=max_iter,
+                           precision=precision, green_variant=variant, check_every=check_every)
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L,f,seed", [(4, 0.5, 3), (64, 0.1, 0), (1024, 0.2, 0), (4096, 0.3, 0)])
+def test_device_mask_bit_exact(L, f, seed):
+    m = pms.device_mask(L, f, seed).cpu().numpy()
+    np.testing.assert_array_equal(m, synth.bernoulli_mask(L, f, seed))
+
+
+def _solver(L, precision, **kw):
+    return pms.Solver(torch.zeros((L, L), dtype=torch.uint8, device="cuda"), gpu_params(L, precision, **kw))
+
+
+def _spec_to_complex(spec, L):
+    """(L, P, 3, 2) device view -> complex (L, L//2+1, 3) numpy."""
+    s = spec.detach().cpu().double().numpy()[:, : L // 2 + 1]
+    return s[..., 0] + 1j * s[..., 1]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
+@pytest.mark.parametrize("L", [4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
+def test_fft_forward_matches_numpy(L, precision, tol):
+    s = _solver(L, precision)
+    rng = np.random.default_rng(L)
+    x = rng.normal(size=(3, L, L))
+    xt = torch.tensor(x, dtype=s.dtype, device="cuda")
+    s.debug_forward(xt)
+    _, spec = s.buffers()
+    got = _spec_to_complex(spec, L)
+    ref = np.moveaxis(np.fft.rfft2(x, axes=(1, 2)), 0, -1)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
+@pytest.mark.parametrize("L", [4, 8, 64, 256, 1024, 4096])
+def test_fft_inverse_matches_numpy(L, precision, tol):
+    s = _solver(L, precision)
+    rng = np.random.default_rng(L + 1)
+    x = rng.normal(size=(3, L, L))
+    X = np.fft.rfft2(x, axes=(1, 2))                     # Hermitian half spectrum
+    _, spec = s.buffers()
+    P = spec.shape[1]
+    buf = np.zeros((L, P, 3, 2))
+    buf[:, : L // 2 + 1, :, 0] = np.moveaxis(X, 0, -1).real
+    buf[:, : L // 2 + 1, :, 1] = np.moveaxis(X, 0, -1).imag
+    spec.copy_(torch.tensor(buf, dtype=s.dtype, device="cuda"))
+    out = torch.empty((3, L, L), dtype=s.dtype, device="cuda")
+    s.debug_inverse(out)
+    got = out.cpu().double().numpy()
+    ref = x * (L * L)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("L", [8, 64, 512])
+def test_green_kernel_matches_oracle(L, variant):
+    s = _solver(L, "fp64", variant=variant)
+    rng = np.random.default_rng(7 + L)
+    _, spec = s.buffers()
+    P = spec.shape[1]
+    t = rng.normal(size=(L, L // 2 + 1, 3)) + 1j * rng.normal(size=(L, L // 2 + 1, 3))
+    buf = np.zeros((L, P, 3, 2))
+    buf[:, : L // 2 + 1, :, 0] = t.real
+    buf[:, : L // 2 + 1, :, 1] = t.imag
+    spec.copy_(torch.tensor(buf, device="cuda"))
+    E = (0.3, -0.2, 0.1)
+    s.debug_green(E)
+    got = _spec_to_complex(spec, L)
+    tau = np.empty((L, L // 2 + 1, 2, 2), complex)
+    tau[..., 0, 0], tau[..., 1, 1] = t[..., 0], t[..., 1]
+    tau[..., 0, 1] = tau[..., 1, 0] = t[..., 2]
+    G = dg.green_on_grid(L, 4.0, 2.0, variant)
+    e = dg.apply_green(G, tau)
+    ref = np.stack([e[..., 0, 0], e[..., 1, 1], e[..., 0, 1]], axis=-1)
+    ref[0, 0] = E
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+def _run_locked(L, f, seed, path, iters, precision, c0=2.0, Y=1.0, variant=0):
+    """GPU with tolerances 0 runs exactly `iters` iterations per step."""
+    mask = synth.bernoulli_mask(L, f, seed)
+    g = pms.Solver(torch.tensor(mask, device="cuda"),
+                   gpu_params(L, precision, c0=c0, Y=Y, tol=0.0, max_iter=iters, variant=variant))
+    o = alm.Solver(mask, oracle_params(L, c0=c0, Y=Y, variant=variant))
+    out = []
+    for E in path:
+        rg = g.step(E)
+        ro = o.step(E, fixed_iters=iters)
+        out.append((rg, ro))
+    g.close()
+    return mask, out
+
+
+@pytest.mark.parametrize("L,f,seed,iters", [(4, 0.25, 1, 5), (8, 0.2, 3, 1), (8, 0.2, 3, 7), (16, 0.1, 2, 25),
+                                            (64, 0.1, 0, 40), (128, 0.3, 5, 15)])
+def test_iteration_locked_fp64(L, f, seed, iters):
+    path = [(0.3, 0.3, 0.0), (0.6, 0.55, 0.05)]
+    _, out = _run_locked(L, f, seed, path, iters, "fp64")
+    for rg, ro in out:
+        assert rg.iters == iters and rg.status == -4
+        assert rel(to_tensor33(rg.sigma), ro.sigma) <= 1e-10
+        assert rel(to_tensor33(rg.eps), ro.eps) <= 1e-10
+        np.testing.assert_allclose(rg.sigma_mean, alm.voigt4(ro.sigma_mean), rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(rg.eps_mean, alm.voigt4(ro.eps_mean), rtol=1e-10, atol=1e-12)
+        assert abs(rg.res_cmp - ro.res_cmp) <= 1e-8 * ro.res_cmp
+        if np.isfinite(ro.res_mac):
+            assert abs(rg.res_mac - ro.res_mac) <= 1e-6 * ro.res_mac + 1e-15
+        else:
+            assert not np.isfinite(rg.res_mac)
+        assert abs(rg.res_eq - ro.res_eq) <= 1e-8 * ro.res_eq
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_iteration_locked_green_variants(variant):
+    _, out = _run_locked(32, 0.2, 4, [(0.4, 0.2, 0.1)], 12, "fp64", variant=variant)
+    rg, ro = out[0]
+    assert rel(to_tensor33(rg.sigma), ro.sigma) <= 1e-10
+
+
+@pytest.mark.parametrize("L,iters", [(64, 50), (256, 30)])
+def test_iteration_locked_fp32(L, iters):
+    path = [(0.0, 0.0, 0.1), (0.0, 0.0, 0.3)]
+    mask, out = _run_locked(L, 0.3, 0, path, iters, "fp32")
+    for rg, ro in out:
+        assert rel(to_tensor33(rg.sigma), ro.sigma) <= 1e-4
+        pl = rg.plastic.cpu().numpy().astype(bool)
+        band = np.abs(ro.margin) <= 1e-5
+        assert np.array_equal(pl[~band], ro.plastic[~band])
+
+
+def test_converged_fp64_stops_where_the_oracle_stops():
+    """Both sides run their own convergence test; same iteration and sigma."""
+    L = 16
+    mask = synth.bernoulli_mask(L, 0.1, 11)
+    E = (0.45, 0.45, 0.0)
+    g = pms.Solver(torch.tensor(mask, device="cuda"), gpu_params(L, "fp64", c0=0.5, tol=1e-10, max_iter=60000))
+    rg = g.step(E)
+    ro = alm.Solver(mask, oracle_params(L, c0=0.5, tol=1e-10, max_iter=60000)).step(E)
+    assert rg.converged and ro.converged
+    assert rg.iters == ro.iters
+    assert rel(to_tensor33(rg.sigma), ro.sigma) <= 1e-10
+    assert rg.res_eq < 1e-10 and rg.res_mac < 1e-10 and rg.res_cmp < 1e-10
+
+
+def test_fp64_workload_first_steps_iteration_locked():
+    """L = 64, f = 0.1 equibiaxial ramp to 3Y/mu in 10 steps, tolerance 1e-8:
+    the GPU runs its own stopping rule; the oracle replays its counts."""
+    L = 64
+    mask = synth.bernoulli_mask(L, 0.1, 0)
+    path = synth.load_path("equibiaxial", 10, 3.0)[:2]
+    g = pms.Solver(torch.tensor(mask, device="cuda"), gpu_params(L, "fp64", tol=1e-8, max_iter=1500))
+    o = alm.Solver(mask, oracle_params(L))
+    for E in path:
+        rg = g.step(E)
+        ro = o.step(E, fixed_iters=rg.iters)
+        assert rel(to_tensor33(rg.sigma), ro.sigma) <= 1e-10
+
+
+def test_homogeneous_medium_exact():
+    L = 64
+    for prec, tol, eta in (("fp64", 1e-14, 1e-8), ("fp32", 1e-6, 1e-6)):
+        g = pms.Solver(torch.zeros((L, L), dtype=torch.uint8, device="cuda"), gpu_params(L, prec, tol=eta))
+        E = (0.7, 0.2, 0.1)
+        r = g.step(E)
+        assert r.converged and r.iters == 2
+        ref = alm.voigt4(hencky.stress(alm.tensor_from_voigt(E), 1.0, 2.0, 1.0))
+        s = r.sigma.cpu().double().numpy()
+        assert np.abs(s - ref[:, None, None]).max() <= tol * np.abs(ref).max()
+
+
+def test_zero_load_and_restart():
+    L = 32
+    mask = synth.bernoulli_mask(L, 0.2, 1)
+    g = pms.Solver(torch.tensor(mask, device="cuda"), gpu_params(L, "fp64", tol=0.0, max_iter=5))
+    g.step((0.3, 0.3, 0.0))
+    r = g.step((0.0, 0.0, 0.0))
+    assert r.converged and r.iters == 0 and r.status == 0
+    assert float(r.sigma.abs().max()) == 0.0
+    # next step warm-starts from the zero state, like the oracle
+    rg = g.step((0.2, 0.1, 0.0))
+    o = alm.Solver(mask, oracle_params(L))
+    o.step((0.3, 0.3, 0.0), fixed_iters=5)
+    o.step((0.0, 0.0, 0.0))
+    ro = o.step((0.2, 0.1, 0.0), fixed_iters=5)
+    assert rel(to_tensor33(rg.sigma), ro.sigma) <= 1e-10
+
+
+def test_voids_stress_free_and_mises_cap():
+    L = 256
+    mask = synth.bernoulli_mask(L, 0.3, 2)
+    g = pms.Solver(torch.tensor(mask, device="cuda"), gpu_params(L, "fp32", tol=0.0, max_iter=30))
+    r = g.step((0.0, 0.0, 1.0))
+    s = r.sigma.cpu().double().numpy()
+    assert np.all(s[:, mask.astype(bool)] == 0.0)
+    seq = hencky.sigma_eq(alm.from_voigt4(np.moveaxis(s, 0, -1)))
+    assert seq.max() <= 1.0 + 1e-5
+    assert r.plastic.cpu().numpy()[mask.astype(bool)].sum() == 0
+
+
+def test_noconv_and_nan_paths():
+    L = 32
+    mask = synth.bernoulli_mask(L, 0.2, 1)
+    g = pms.Solver(torch.tensor(mask, device="cuda"), gpu_params(L, "fp64", tol=1e-12, max_iter=1))
+    r = g.step((0.3, 0.3, 0.0))
+    assert r.status == -4 and r.iters == 1 and not r.converged
+    eps, _ = g.buffers()
+    eps[0, 3, 5] = float("nan")
+    r = g.step((0.3, 0.3, 0.0))
+    assert r.status == -5 and not r.converged
+
+
+def test_invalid_arguments():
+    from paper_0802_2488_amd._lib import PmError
+    with pytest.raises(PmError):
+        pms.Solver(torch.zeros((48, 48), dtype=torch.uint8, device="cuda"), gpu_params(48, "fp32"))
