@@ -38,7 +38,23 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=500)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only run a plain device copy of 256 MiB five times (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_reference():
+    """Plain device-to-device copy of known size, for scaling HBM byte counters."""
+    import torch
+
+    n = 64 * 1024 * 1024                     # 64 Mi floats = 256 MiB per buffer
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_reference_bytes_read": 4 * n, "copy_reference_bytes_written": 4 * n,
+                      "launches": 5}), flush=True)
 
 
 def algorithmic_bytes(L: int, fs: int):
@@ -118,6 +134,9 @@ def cpu_baseline(L):
 
 def main():
     a = parse()
+    if a.copy_ref:
+        copy_reference()
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(the solve is per-GPU; see the sharding notes in DESIGN.md)"}))

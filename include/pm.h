@@ -167,27 +167,44 @@ int pm_solver_destroy(pm_solver* solver);
  */
 int pm_bernoulli_mask(uint8_t* dst, int32_t L, double f, uint64_t seed, int32_t on_device, void* stream);
 
-/* Complex numbers per row of the internal half spectrum (>= L/2 + 1). */
-int64_t pm_spectrum_pitch(int32_t L);
+/*
+ * Tile width WT of the internal half spectrum for this size and precision
+ * (negative PM_EINVAL on invalid arguments).  The half spectrum holds, per
+ * component c (0: 11, 1: 22, 2: 12), L/2 columns m1 = 0..L/2-1 of L rows
+ * m2 = 0..L-1 of complex values in the field precision, at complex index
+ *     (((m1 / WT) * L + m2) * WT + m1 % WT) * 3 + c.
+ * Row transforms of real fields have real bins m1 = 0 and m1 = L/2; column
+ * m1 = 0 stores bin 0 in its real part and bin L/2 in its imaginary part.
+ * After a column transform that column holds the transform of that packed
+ * complex sequence.
+ */
+int32_t pm_spectrum_tile(int32_t L, int32_t precision);
 
 /*
  * Kernel-level entry points on a solver's own buffers (used to check each
- * kernel in isolation).  The half spectrum is L rows of pm_spectrum_pitch(L)
- * momenta m1 = 0..L/2, each holding three interleaved complex values
- * (components 11, 22, 12) in the field precision; row index m2 = 0..L-1.
+ * kernel in isolation), with the half spectrum in the layout of
+ * pm_spectrum_tile.
  *
- * pm_solver_buffers   device pointers of the strain state (4 planes) and
- *                     of the half spectrum.
+ * pm_solver_buffers   device pointers of the solver state and of the half
+ *                     spectrum.  The state is the stress of the last iterate
+ *                     (4 planes), which is also the augmented-Lagrangian
+ *                     multiplier; the strain is recovered from it and the
+ *                     stored polarisation when outputs are written.
  * pm_debug_forward    d_real: 3 planes (11, 22, 12).  Spectrum := the 2-D
- *                     DFT sum_x f(x) exp(-i q.x) of each plane (rows m1 <= L/2).
+ *                     DFT sum_x f(x) exp(-i q.x) of each plane (packed
+ *                     column 0 as described above).
  * pm_debug_inverse    d_real := the unnormalised inverse 2-D DFT
  *                     sum_q F(q) exp(+i q.x) of the Hermitian-extended
- *                     spectrum (L^2 times numpy.fft.irfft2).
+ *                     spectrum (L^2 times numpy.fft.irfft2); the spectrum
+ *                     buffer is overwritten.
  * pm_debug_green      spectrum(q) := G(q):spectrum(q) (eq. 3, built from
- *                     mu0, lambda0, green_variant) for q != 0 and E at q = 0.
+ *                     mu0, lambda0, green_variant) for q != 0 and E at q = 0;
+ *                     column 0 is split into its m1 = 0 and m1 = L/2 parts by
+ *                     conjugate symmetry in m2, each gets its own tensor, and
+ *                     the results are packed again.
  * All three issue work on the solver's stream and synchronise it.
  */
-int pm_solver_buffers(pm_solver* solver, void** d_eps, void** d_spectrum);
+int pm_solver_buffers(pm_solver* solver, void** d_state, void** d_spectrum);
 
 /*
  * Per-kernel device time of the iterations a solver has run while timing was

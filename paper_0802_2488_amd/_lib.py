@@ -11,7 +11,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpm.so")
+LIB_PATH = os.environ.get("PM_LIB_PATH") or os.path.join(HERE, "libpm.so")
 
 PM_OK, PM_EINVAL, PM_EDEVICE, PM_ENOCONV, PM_ENAN, PM_EBUSY = 0, -1, -3, -4, -5, -6
 PM_FP32, PM_FP64 = 0, 1
@@ -58,7 +58,7 @@ SIGNATURES = [
     ("pm_solver_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("pm_bernoulli_mask", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]),
-    ("pm_spectrum_pitch", ctypes.c_int64, [ctypes.c_int32]),
+    ("pm_spectrum_tile", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
     ("pm_solver_buffers", ctypes.c_int,
      [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
     ("pm_solver_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(PmKernelTiming)]),

@@ -19,16 +19,20 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    """Compile every source to an object (in parallel) and link libpm.so."""
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, jobs: int = 4, extra=(), out=None, objdir=None) -> str:
+    """Compile every source to an object (in parallel) and link libpm.so.
+
+    extra: additional compiler flags (e.g. -DPM_ROW_WPE=4 tuning knobs);
+    out / objdir: alternative output library and object directory."""
+    objdir = objdir or os.path.join(HERE, "_build")
+    lib_out = out or LIB
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
@@ -42,11 +46,11 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             sys.stderr.write(out)
     if failed:
         raise RuntimeError("hipcc compilation failed")
-    tmp = LIB + ".tmp"
+    tmp = lib_out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_out)
+    return lib_out
 
 
 if __name__ == "__main__":

@@ -41,8 +41,8 @@ bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t eps, spec, tw, ktab, part, part2, state, total;
-  long pitch;
+  size_t sig, spec, xbuf, tw, ktab, part, part2, state, total;
+  int tile;
   int nrow, ndiv;
 };
 
@@ -73,17 +73,18 @@ Layout make_layout(const pm_params& q) {
   Layout lo{};
   const size_t L = (size_t)q.L;
   const size_t fs = q.precision == PM_FP64 ? 8 : 4;
-  lo.pitch = pm_spectrum_pitch(q.L);
+  lo.tile = pm_spectrum_tile(q.L, q.precision);
   lo.nrow = q.precision == PM_FP64 ? pm::row_grid<double>(q.L) : pm::row_grid<float>(q.L);
-  lo.ndiv = pm::div_grid(q.L);
+  lo.ndiv = std::max(pm::div_grid(q.L), 4 * lo.nrow);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = align_up(off + bytes, 256);
     return o;
   };
-  lo.eps = take(4 * L * L * fs);
-  lo.spec = take(L * (size_t)lo.pitch * 3 * 2 * fs);
+  lo.sig = take(4 * L * L * fs);
+  lo.spec = take(L * (L / 2) * 3 * 2 * fs);
+  lo.xbuf = take(3 * L * 2 * fs);
   lo.tw = take(L * 2 * fs);
   lo.ktab = take(L * 2 * fs);
   lo.part = take((size_t)lo.nrow * pm::NPART * sizeof(double));
@@ -103,12 +104,13 @@ struct pm_solver {
   int device;
   const uint8_t* mask;
   char* ws;
-  void* eps;
+  void* sig;       // state: stress of the last iterate (4 planes)
   void* spec;
   void* tw;
   void* ktab;
   double* part;
   double* part2;
+  void* xbuf;
   DevState* st;
   DevState* hst;   // pinned host copies (two slots)
   hipEvent_t ev[2];
@@ -146,11 +148,10 @@ pm::RowArgs<T> row_args(pm_solver* s, int mode, const double* E, bool with_state
   pm::RowArgs<T> a{};
   a.spec = (pm::cx<T>*)s->spec;
   a.tw = (const pm::cx<T>*)s->tw;
-  a.eps = (T*)s->eps;
+  a.sig = (T*)s->sig;
   a.mask = s->mask;
   a.partials = s->part;
   a.state = with_state ? s->st : nullptr;
-  a.pitch = s->lo.pitch;
   a.mode = mode;
   for (int i = 0; i < 3; ++i) a.E[i] = E ? E[i] : 0.0;
   a.prm = s->prm;
@@ -164,7 +165,7 @@ pm::ColArgs<T> col_args(pm_solver* s, int mode, double scale, const double* E, b
   a.tw = (const pm::cx<T>*)s->tw;
   a.ktab = (const pm::cx<T>*)s->ktab;
   a.state = with_state ? s->st : nullptr;
-  a.pitch = s->lo.pitch;
+  a.xbuf = (pm::cx<T>*)s->xbuf;
   a.mode = mode;
   const int v = s->p.green_variant;
   a.flip1 = (v == 1 || v == 2) ? 1 : 0;
@@ -187,7 +188,7 @@ int iterate_once(pm_solver* s, int slot_in_chunk) {
   PM_HIP(pm::launch_row<T>(L, row_args<T>(s, pm::ROW_ITER, nullptr, true), s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[2], s->stream));
   PM_HIP(pm::launch_reduce(s->part, s->lo.nrow, s->st, s->prm, s->stream));
-  PM_HIP(pm::launch_div<T>((const T*)s->eps, s->mask, s->part2, s->st, s->prm, L, 0, s->stream));
+  PM_HIP(pm::launch_div<T>((const T*)s->sig, s->part2, s->st, s->prm, L, 0, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[3], s->stream));
   return PM_OK;
 }
@@ -209,6 +210,22 @@ int collect_timing(pm_solver* s, int executed) {
   return PM_OK;
 }
 
+// Per-step outputs (strain recovered from the stored stress and tau) and the
+// FP64 mean strain into the device state.
+template <typename T>
+int emit(pm_solver* s, pm_step_out* out) {
+  auto ra = row_args<T>(s, pm::ROW_EMIT, nullptr, false);
+  if (out) {
+    ra.sig_out = (T*)out->sigma;
+    ra.eps_out = (T*)out->eps;
+    ra.plastic_out = out->plastic;
+  }
+  ra.partials = s->part2;
+  PM_HIP(pm::launch_row<T>(s->p.L, ra, s->stream));
+  PM_HIP(pm::launch_reduce_emit(s->part2, s->lo.nrow, s->st, (double)s->p.L * s->p.L, s->stream));
+  return PM_OK;
+}
+
 template <typename T>
 int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
   const int L = s->p.L;
@@ -219,9 +236,10 @@ int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
     const double z[3] = {0.0, 0.0, 0.0};
     PM_HIP(pm::launch_row<T>(L, row_args<T>(s, pm::ROW_INIT, z, false), s->stream));
     s->started = true;
-    if (out && (out->sigma || out->eps || out->plastic))
-      PM_HIP(pm::launch_emit<T>((const T*)s->eps, s->mask, (T*)out->sigma, (T*)out->eps, out->plastic, s->prm, L,
-                                s->stream));
+    if (out && (out->sigma || out->eps || out->plastic)) {
+      int rc = emit<T>(s, out);
+      if (rc != PM_OK) return rc;
+    }
     PM_HIP(hipStreamSynchronize(s->stream));
     if (out) {
       for (int i = 0; i < 4; ++i) out->sigma_mean[i] = out->eps_mean[i] = 0.0;
@@ -276,19 +294,19 @@ int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
       fin = pend;
     }
   }
-  DevState hs = s->hst[fin];
-  if (!hs.halted) return fail(PM_EDEVICE, "device did not halt after max_iter iterations");
-  if (hs.status != pm::ST_CONVERGED) {
+  if (!s->hst[fin].halted) return fail(PM_EDEVICE, "device did not halt after max_iter iterations");
+  if (s->hst[fin].status != pm::ST_CONVERGED) {
     // report the equilibrium indicator of the final iterate
-    PM_HIP(pm::launch_div<T>((const T*)s->eps, s->mask, s->part2, s->st, s->prm, L, 1, s->stream));
-    PM_HIP(hipMemcpyAsync(&s->hst[0], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
-    PM_HIP(hipStreamSynchronize(s->stream));
-    hs.res_eq = s->hst[0].res_eq;
+    PM_HIP(pm::launch_div<T>((const T*)s->sig, s->part2, s->st, s->prm, L, 1, s->stream));
   }
-  if (out && (out->sigma || out->eps || out->plastic))
-    PM_HIP(pm::launch_emit<T>((const T*)s->eps, s->mask, (T*)out->sigma, (T*)out->eps, out->plastic, s->prm, L,
-                              s->stream));
+  // outputs and <eps> (always), then the final state
+  {
+    int rc = emit<T>(s, out);
+    if (rc != PM_OK) return rc;
+  }
+  PM_HIP(hipMemcpyAsync(&s->hst[0], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
   PM_HIP(hipStreamSynchronize(s->stream));
+  const DevState hs = s->hst[0];
   int rc = PM_OK;
   if (hs.status == pm::ST_NOCONV) rc = PM_ENOCONV;
   if (hs.status == pm::ST_NAN) rc = PM_ENAN;
@@ -354,7 +372,12 @@ const char* pm_status_string(int status) {
 
 const char* pm_last_error(void) { return g_err.c_str(); }
 
-int64_t pm_spectrum_pitch(int32_t L) { return ((int64_t)(L / 2 + 1) + 15) / 16 * 16; }
+int32_t pm_spectrum_tile(int32_t L, int32_t precision) {
+  if (!is_pow2(L) || L < 4 || L > PM_MAX_L) return fail(PM_EINVAL, "L = %d must be a power of two in [4, %d]", L, PM_MAX_L);
+  if (precision == PM_FP32) return pm::tile_width<float>(L);
+  if (precision == PM_FP64) return pm::tile_width<double>(L);
+  return fail(PM_EINVAL, "precision must be PM_FP32 or PM_FP64");
+}
 
 size_t pm_workspace_bytes(const pm_params* params) {
   pm_params q;
@@ -381,12 +404,13 @@ int pm_solver_create(pm_solver** out, const pm_params* params, const uint8_t* d_
   s->stream = (hipStream_t)stream;
   s->mask = d_void_mask;
   s->ws = (char*)d_workspace;
-  s->eps = s->ws + lo.eps;
+  s->sig = s->ws + lo.sig;
   s->spec = s->ws + lo.spec;
   s->tw = s->ws + lo.tw;
   s->ktab = s->ws + lo.ktab;
   s->part = (double*)(s->ws + lo.part);
   s->part2 = (double*)(s->ws + lo.part2);
+  s->xbuf = s->ws + lo.xbuf;
   s->st = (DevState*)(s->ws + lo.state);
   s->started = false;
   const long L2 = (long)q.L * q.L;
@@ -397,7 +421,6 @@ int pm_solver_create(pm_solver** out, const pm_params* params, const uint8_t* d_
   d.K = q.lambda + 2.0 * q.mu / 3.0;
   d.K0 = q.lambda0 + 2.0 * q.mu0 / 3.0;
   d.sy = std::sqrt(2.0 / 3.0) * q.Y;
-  d.thr_rho = std::sqrt(2.0 / 3.0) * q.Y * (q.mu + q.mu0) / q.mu;
   d.npx = (double)L2;
   d.eta_eq = q.eta_eq; d.eta_mac = q.eta_mac; d.eta_cmp = q.eta_cmp;
   d.max_iter = q.max_iter;
@@ -460,7 +483,7 @@ int pm_solver_timing(pm_solver* s, int32_t enable, pm_kernel_timing* out) {
 
 int pm_solver_buffers(pm_solver* s, void** d_eps, void** d_spectrum) {
   if (!s) return fail(PM_EINVAL, "solver is NULL");
-  if (d_eps) *d_eps = s->eps;
+  if (d_eps) *d_eps = s->sig;
   if (d_spectrum) *d_spectrum = s->spec;
   return PM_OK;
 }

@@ -133,6 +133,17 @@ __device__ __forceinline__ void dft_split(cx<T>* v) {
   }
 }
 
+// Dependency fence on register-resident values: the empty asm "redefines"
+// every element, so no arithmetic can move across it in either direction.
+// Used between the phases of a fused kernel (load, transform, pointwise
+// work) to keep the compiler from interleaving them, which otherwise raises
+// register pressure into spills.
+template <typename T, int R>
+__device__ __forceinline__ void fence(cx<T> (&z)[R]) {
+#pragma unroll
+  for (int i = 0; i < R; ++i) asm volatile("" : "+v"(z[i].re), "+v"(z[i].im));
+}
+
 // ---------------------------------------------------------------------------
 // Radix plan: N = RMAX^s * rem (rem < RMAX); stages RMAX, ..., rem, RMAX.
 template <int N, int RMAX>
@@ -267,10 +278,11 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[RMAX], T* lre, T* lim, int
 // threads; every thread of the block must call it (it contains barriers).
 template <int DIR, typename T, int N, int RMAX>
 __device__ __forceinline__ void fft(cx<T> (&v)[RMAX], T* lre, T* lim, int t, const cx<T>* tw) {
-  // An opaque copy of the table pointer per transform keeps the compiler from
-  // holding one transform's twiddles live across unrelated work.
+  // An opaque copy of the table pointer behind a compiler memory barrier:
+  // twiddle loads cannot be hoisted out of the transform and held live
+  // across unrelated work.
   const cx<T>* twp = tw;
-  asm volatile("" : "+s"(twp));
+  asm volatile("" : "+s"(twp) : : "memory");
   fft_stages<DIR, T, N, RMAX, 0>(v, lre, lim, t, twp);
 }
 

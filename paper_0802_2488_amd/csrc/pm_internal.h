@@ -7,7 +7,7 @@
 
 namespace pm {
 
-enum RowMode { ROW_ITER = 0, ROW_INIT = 1, ROW_FWD = 2, ROW_INV = 3 };
+enum RowMode { ROW_ITER = 0, ROW_INIT = 1, ROW_FWD = 2, ROW_INV = 3, ROW_EMIT = 4 };
 enum ColMode { COL_FWD = 1, COL_GREEN = 2, COL_INV = 4, COL_ALL = 7 };
 enum Status { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NOCONV = 2, ST_NAN = 3 };
 
@@ -26,7 +26,7 @@ struct DevState {
 
 struct DevParams {
   double mu, lam, Y, mu0, lam0, K, K0;
-  double sy, thr_rho;
+  double sy;
   double npx;
   double eta_eq, eta_mac, eta_cmp;
   int32_t max_iter, L;
@@ -36,13 +36,15 @@ template <typename T>
 struct RowArgs {
   cx<T>* spec;
   const cx<T>* tw;
-  T* eps;
+  T* sig;          // state: stress of the last iterate (= multiplier), 4 planes
   const uint8_t* mask;
   double* partials;
   DevState* state;
   const T* real_in;
   T* real_out;
-  long pitch;
+  T* sig_out;      // ROW_EMIT outputs (may be null)
+  T* eps_out;
+  uint8_t* plastic_out;
   int mode;
   double E[3];
   DevParams prm;
@@ -54,7 +56,7 @@ struct ColArgs {
   const cx<T>* tw;
   const cx<T>* ktab;
   DevState* state;
-  long pitch;
+  cx<T>* xbuf;   // 3 L values: transform of the packed column 0
   int mode;
   int flip1, flip2;
   double lam0, mu0, scale;
@@ -67,15 +69,15 @@ template <typename T>
 hipError_t launch_col(int L, const ColArgs<T>& a, hipStream_t st);
 template <typename T>
 int row_grid(int L);
+template <typename T>
+int tile_width(int L);
 int div_grid(int L);
 hipError_t launch_reduce(const double* partials, int nblk, DevState* st, const DevParams& prm, hipStream_t s);
 template <typename T>
-hipError_t launch_div(const T* eps, const uint8_t* mask, double* partials, DevState* st, const DevParams& prm, int L,
-                      int force, hipStream_t s);
+hipError_t launch_div(const T* sig, double* partials, DevState* st, const DevParams& prm, int L, int force,
+                      hipStream_t s);
 hipError_t launch_begin(DevState* st, const double* E, double floor_s, hipStream_t s);
-template <typename T>
-hipError_t launch_emit(const T* eps, const uint8_t* mask, T* sig, T* eps_out, uint8_t* pl, const DevParams& prm,
-                       int L, hipStream_t s);
+hipError_t launch_reduce_emit(const double* partials, int nblk, DevState* st, double npx, hipStream_t s);
 hipError_t launch_mask(uint8_t* out, long npx, double f, uint64_t seed, hipStream_t s);
 
 }  // namespace pm

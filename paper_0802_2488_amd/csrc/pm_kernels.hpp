@@ -21,6 +21,32 @@
 #include "pm_fft.hpp"
 #include "pm_internal.h"
 
+// Tuning knobs (compile-time; the defaults are the measured best on MI355X).
+#ifndef PM_ROW_R32
+#define PM_ROW_R32 8          // row-pass radix, FP32
+#endif
+#ifndef PM_ROW_R64
+#define PM_ROW_R64 4          // row-pass radix, FP64
+#endif
+#ifndef PM_ROW_TPF_MAX
+#define PM_ROW_TPF_MAX 512    // most threads per row-pass transform
+#endif
+#ifndef PM_ROW_WPE
+#define PM_ROW_WPE 2          // minimum waves per SIMD requested for the row pass
+#endif
+#ifndef PM_COL_R32
+#define PM_COL_R32 16         // column-pass radix, FP32, L >= 2048
+#endif
+#ifndef PM_COL_R64
+#define PM_COL_R64 8          // column-pass radix, FP64, L >= 2048
+#endif
+#ifndef PM_COL_W32
+#define PM_COL_W32 2          // columns per block (= spectrum tile width), FP32, long columns
+#endif
+#ifndef PM_COL_WPE
+#define PM_COL_WPE 2
+#endif
+
 namespace pm {
 
 // ---------------------------------------------------------------------------
@@ -29,51 +55,64 @@ template <typename T>
 struct Mat {
   T mu, lam, Y, mu0, lam0, K, K0;
   T sy;        // sqrt(2/3) Y: Frobenius norm of the capped stress deviator
-  T thr_rho;   // sqrt(2/3) Y (mu + mu0) / mu: plastic iff |dev R| exceeds it
-  T inv2mu_mu0, inv2mu0, inv3KK0;
+  T cel;       // mu / (mu + mu0): deviator ratio s / dev R on the elastic branch
+  T inv2mu0, inv3KK0, inv3K, inv2lm0;
 };
 
 template <typename T>
 __device__ __forceinline__ Mat<T> make_mat(const DevParams& p) {
   Mat<T> m;
   m.mu = (T)p.mu; m.lam = (T)p.lam; m.Y = (T)p.Y; m.mu0 = (T)p.mu0; m.lam0 = (T)p.lam0;
-  m.K = (T)p.K; m.K0 = (T)p.K0; m.sy = (T)p.sy; m.thr_rho = (T)p.thr_rho;
-  m.inv2mu_mu0 = (T)(1.0 / (2.0 * (p.mu + p.mu0)));
+  m.K = (T)p.K; m.K0 = (T)p.K0; m.sy = (T)p.sy;
+  m.cel = (T)(p.mu / (p.mu + p.mu0));
   m.inv2mu0 = (T)(1.0 / (2.0 * p.mu0));
   m.inv3KK0 = (T)(1.0 / (3.0 * (p.K + p.K0)));
+  m.inv3K = (T)(1.0 / (3.0 * p.K));
+  m.inv2lm0 = (T)(1.0 / (2.0 * (p.lam0 + p.mu0)));
   return m;
 }
 
-// Hencky-Mises stress of a matrix pixel; eps = (11, 22, 33, 12).
+// 1 / sqrt(x): the hardware estimate in FP32 (~1 ulp), exact in FP64.
+__device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
+// Hencky-Mises stress of a matrix pixel; eps = (11, 22, 33, 12).  The
+// deviator is 2 mu dev(eps) capped at Frobenius norm sqrt(2/3) Y:
+// s = min(2 mu, sqrt(2/3) Y / |dev eps|) dev eps.  Returns the plastic flag
+// (strictly beyond the cap).
 template <typename T>
 __device__ __forceinline__ bool hencky(const T* e, T* s, const Mat<T>& m) {
   const T t3 = (e[0] + e[1] + e[2]) * (T)(1.0 / 3.0);
   const T d0 = e[0] - t3, d1 = e[1] - t3, d2 = e[2] - t3, d3 = e[3];
-  const T nd = sqrt(d0 * d0 + d1 * d1 + d2 * d2 + (T)2 * d3 * d3);
-  const bool plastic = (T)2 * m.mu * nd > m.sy;
-  const T sc = plastic ? m.sy / nd : (T)2 * m.mu;
+  const T cap = m.sy * rsq(d0 * d0 + d1 * d1 + d2 * d2 + (T)2 * d3 * d3);
+  const T tm = (T)2 * m.mu;
+  const bool plastic = cap < tm;
+  const T sc = plastic ? cap : tm;
   const T pr = (T)3 * m.K * t3;
   s[0] = pr + sc * d0; s[1] = pr + sc * d1; s[2] = pr + sc * d2; s[3] = sc * d3;
   return plastic;
 }
 
-// Pointwise step: solve S(eps) + C0:eps = S(eps_old) + C0:e for one pixel.
-// e = (e11, e22, e12) with e33 = 0.  Outputs eps_new, sigma and the in-plane
-// polarisation tau = sigma - C0:eps_new.
+// Pointwise step of one pixel: solve S(eps) + C0:eps = R with
+// R = lambda + C0:e, where lambda (the multiplier, equal to the stress of the
+// previous iterate) is the stored state and e = (e11, e22, e12), e33 = 0.
+// Volumetric part: tr eps = tr R / (3 (K + K0)).  Deviatoric part with
+// r = dev R: s = c r, c = min(mu / (mu + mu0), sqrt(2/3) Y / |r|) (the elastic
+// and the capped branch in one formula), dev eps = (r - s) / (2 mu0).
+// Voids carry no stress: eps = e (in plane), eps33 = 0.
+// Outputs the new stress (the next multiplier), eps and tau = sigma - C0:eps.
 template <typename T>
-__device__ __forceinline__ void alm_point(const T* e, const T* eo, bool is_void, const Mat<T>& m, T* en, T* sg,
+__device__ __forceinline__ void alm_point(const T* e, const T* la, bool is_void, const Mat<T>& m, T* en, T* sg,
                                           T* tau) {
   if (is_void) {
     en[0] = e[0]; en[1] = e[1]; en[2] = (T)0; en[3] = e[2];
     sg[0] = sg[1] = sg[2] = sg[3] = (T)0;
-    const T tr = e[0] + e[1];
-    tau[0] = -(m.lam0 * tr + (T)2 * m.mu0 * e[0]);
-    tau[1] = -(m.lam0 * tr + (T)2 * m.mu0 * e[1]);
+    const T tr = m.lam0 * (e[0] + e[1]);
+    tau[0] = -(tr + (T)2 * m.mu0 * e[0]);
+    tau[1] = -(tr + (T)2 * m.mu0 * e[1]);
     tau[2] = -((T)2 * m.mu0 * e[2]);
     return;
   }
-  T la[4];
-  hencky(eo, la, m);
   const T tre = m.lam0 * (e[0] + e[1]);
   const T R0 = la[0] + tre + (T)2 * m.mu0 * e[0];
   const T R1 = la[1] + tre + (T)2 * m.mu0 * e[1];
@@ -81,26 +120,44 @@ __device__ __forceinline__ void alm_point(const T* e, const T* eo, bool is_void,
   const T R3 = la[3] + (T)2 * m.mu0 * e[2];
   const T trR3 = (R0 + R1 + R2) * (T)(1.0 / 3.0);
   const T r0 = R0 - trR3, r1 = R1 - trR3, r2 = R2 - trR3, r3 = R3;
-  const T rho = sqrt(r0 * r0 + r1 * r1 + r2 * r2 + (T)2 * r3 * r3);
+  const T cap = m.sy * rsq(r0 * r0 + r1 * r1 + r2 * r2 + (T)2 * r3 * r3);
+  const T c = cap < m.cel ? cap : m.cel;
+  const T s0 = c * r0, s1 = c * r1, s2 = c * r2, s3 = c * r3;
   const T tr_eps = (T)3 * trR3 * m.inv3KK0;
-  T s0, s1, s2, s3, d0, d1, d2, d3;
-  if (rho <= m.thr_rho) {
-    d0 = r0 * m.inv2mu_mu0; d1 = r1 * m.inv2mu_mu0; d2 = r2 * m.inv2mu_mu0; d3 = r3 * m.inv2mu_mu0;
-    const T tm = (T)2 * m.mu;
-    s0 = tm * d0; s1 = tm * d1; s2 = tm * d2; s3 = tm * d3;
-  } else {
-    const T c = m.sy / rho;
-    s0 = c * r0; s1 = c * r1; s2 = c * r2; s3 = c * r3;
-    d0 = (r0 - s0) * m.inv2mu0; d1 = (r1 - s1) * m.inv2mu0; d2 = (r2 - s2) * m.inv2mu0; d3 = (r3 - s3) * m.inv2mu0;
-  }
   const T t3 = tr_eps * (T)(1.0 / 3.0);
-  en[0] = d0 + t3; en[1] = d1 + t3; en[2] = d2 + t3; en[3] = d3;
+  en[0] = (r0 - s0) * m.inv2mu0 + t3;
+  en[1] = (r1 - s1) * m.inv2mu0 + t3;
+  en[2] = (r2 - s2) * m.inv2mu0 + t3;
+  en[3] = (r3 - s3) * m.inv2mu0;
   const T pr = m.K * tr_eps;
   sg[0] = pr + s0; sg[1] = pr + s1; sg[2] = pr + s2; sg[3] = s3;
   const T c0t = m.lam0 * tr_eps;
   tau[0] = sg[0] - (c0t + (T)2 * m.mu0 * en[0]);
   tau[1] = sg[1] - (c0t + (T)2 * m.mu0 * en[1]);
   tau[2] = sg[3] - (T)2 * m.mu0 * en[3];
+}
+
+// Strain from the stored stress and the polarisation tau = sigma - C0:eps of
+// the same iterate.  Matrix: tr eps = tr sigma / (3K); in plane
+// eps_ab = (sigma_ab - tau_ab - lambda0 tr eps delta_ab) / (2 mu0);
+// eps33 = tr eps - eps11 - eps22.  Voids (sigma = 0, eps = e, eps33 = 0):
+// tr = -(tau11 + tau22) / (2 (lambda0 + mu0)), eps_ab = -(tau_ab + lambda0
+// tr delta_ab) / (2 mu0).
+template <typename T>
+__device__ __forceinline__ void strain_from(const T* sg, const T* tau, bool is_void, const Mat<T>& m, T* en) {
+  if (is_void) {
+    const T tr = -(tau[0] + tau[1]) * m.inv2lm0;
+    en[0] = -(tau[0] + m.lam0 * tr) * m.inv2mu0;
+    en[1] = -(tau[1] + m.lam0 * tr) * m.inv2mu0;
+    en[2] = (T)0;
+    en[3] = -tau[2] * m.inv2mu0;
+    return;
+  }
+  const T tr = (sg[0] + sg[1] + sg[2]) * m.inv3K;
+  en[0] = (sg[0] - tau[0] - m.lam0 * tr) * m.inv2mu0;
+  en[1] = (sg[1] - tau[1] - m.lam0 * tr) * m.inv2mu0;
+  en[3] = (sg[3] - tau[2]) * m.inv2mu0;
+  en[2] = tr - en[0] - en[1];
 }
 
 // ---------------------------------------------------------------------------
@@ -136,14 +193,33 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __re
   }
 }
 
-// Row-pass output: split the complex transform of x + i y into the half
-// spectra X (component cx of row qx) and Y (component cy of row qy).
-template <typename T, int L, int RMAX>
-__device__ __forceinline__ void split_store(const cx<T> (&z)[RMAX], T* lre, T* lim, int t, cx<T>* qx, int cxi,
-                                            cx<T>* qy, int cyi) {
+// ---------------------------------------------------------------------------
+// Half-spectrum layout.  Row transforms of real rows have real bins m1 = 0
+// and m1 = L/2; the Nyquist value is stored in the imaginary slot of bin 0,
+// so a row holds exactly L/2 complex bins per component.  Columns are tiled
+// WT at a time so a column block's data is one contiguous run:
+//   index(m1, m2, c) = (((m1 / WT) * L + m2) * WT + m1 % WT) * 3 + c.
+template <int L, int WT>
+__device__ __forceinline__ unsigned sidx(int m1, int m2) {
+  return ((unsigned)((m1 / WT) * L + m2) * WT + (unsigned)(m1 % WT)) * 3u;
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of logical work items so neighbours, which share cache
+  // lines, meet in the same L2 at about the same time.
+  const int x = b & 7, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Row-pass output: split the complex transform Z of x + i y into the half
+// spectra X (component cxi of row qx) and Y (component cyi of row qy);
+// X[m] = (Z[m] + conj Z[L-m]) / 2, Y[m] = (Z[m] - conj Z[L-m]) / (2i), with
+// the real Nyquist values packed into the imaginary slots of bin 0.
+template <typename T, int L, int RMAX, int WT>
+__device__ __forceinline__ void split_store(const cx<T> (&z)[RMAX], T* lre, T* lim, int t, cx<T>* __restrict__ spec,
+                                            int rx, int cxi, int ry, int cyi) {
   constexpr int TPF = L / RMAX;
-  constexpr int H = L / 2 + 1;
-  constexpr int NOUT = RMAX / 2 + 1;
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < RMAX; ++s) {
@@ -153,84 +229,130 @@ __device__ __forceinline__ void split_store(const cx<T> (&z)[RMAX], T* lre, T* l
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < NOUT; ++k) {
+  for (int k = 0; k < RMAX / 2; ++k) {
     const int mm = t + TPF * k;
-    if (mm < H) {
-      const int i0 = lpad(mm), i1 = lpad((L - mm) & (L - 1));
-      const cx<T> zm = {lre[i0], lim[i0]};
-      const cx<T> zr = {lre[i1], -lim[i1]};   // conj Z[L - m]
-      const cx<T> d = zm - zr;
-      qx[mm * 3 + cxi] = cscale(zm + zr, (T)0.5);
-      qy[mm * 3 + cyi] = {d.im * (T)0.5, -d.re * (T)0.5};
+    const int i0 = lpad(mm), i1 = lpad((L - mm) & (L - 1));
+    const cx<T> zm = {lre[i0], lim[i0]};
+    const cx<T> zr = {lre[i1], -lim[i1]};   // conj Z[L - m]
+    const cx<T> d = zm - zr;
+    cx<T> X = cscale(zm + zr, (T)0.5);
+    cx<T> Y = {d.im * (T)0.5, -d.re * (T)0.5};
+    if (mm == 0) {
+      const int ih = lpad(L / 2);
+      X.im = lre[ih];   // Re Z[L/2]: Nyquist bin of x
+      Y.im = lim[ih];   // Im Z[L/2]: Nyquist bin of y
     }
+    spec[sidx<L, WT>(mm, rx) + cxi] = X;
+    spec[sidx<L, WT>(mm, ry) + cyi] = Y;
   }
+}
+
+// Hermitian extension of a packed row spectrum at bin m in [0, L).
+template <typename T, int L, int WT>
+__device__ __forceinline__ cx<T> load_bin(const cx<T>* __restrict__ spec, int m, int row, int c) {
+  if (m == 0) return {spec[sidx<L, WT>(0, row) + c].re, (T)0};
+  if (m == L / 2) return {spec[sidx<L, WT>(0, row) + c].im, (T)0};
+  if (m < L / 2) return spec[sidx<L, WT>(m, row) + c];
+  return cconj(spec[sidx<L, WT>(L - m, row) + c]);
 }
 
 // ---------------------------------------------------------------------------
 // Row pass.  A team of TPF = L / RMAX threads owns rows a = 2p and b = 2p + 1
 // and three complex length-L signals: Za = 11a + i 22a, Zb = 11b + i 22b,
-// Zc = 12a + i 12b (two real rows per complex transform).
-template <typename T, int L, int RMAX, int TEAMS, int MODE>
-__global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(2))) k_row(RowArgs<T> a) {
+// Zc = 12a + i 12b (two real rows per complex transform).  Modes:
+//   ROW_ITER  inverse row FFT -> e; pointwise step on the stored stress;
+//             new stress stored; tau forward-transformed back
+//   ROW_INIT  stress S(E) (0 on voids) stored; tau = sigma - C0:E transformed
+//   ROW_EMIT  inverse row FFT of the stored tau; strain recovered from the
+//             stress and tau; per-step outputs and sums of the strain
+//   ROW_FWD / ROW_INV  plain row transforms of three real planes (checks)
+template <typename T, int L, int RMAX, int TEAMS, int WT, int MODE>
+__global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_ROW_WPE))) k_row(RowArgs<T> a) {
   constexpr int TPF = L / RMAX;
-  constexpr int H = L / 2 + 1;
+  constexpr int BS = TEAMS * TPF;
   constexpr int LS = LdsSize<L>::value;
   constexpr int LOAD_GROUP = RMAX >= 4 ? 4 : RMAX;   // unrolled iterations whose loads may be in flight together
+  constexpr bool LOADS_SPEC = MODE == ROW_ITER || MODE == ROW_INV || MODE == ROW_EMIT;
+  constexpr bool POINTWISE = MODE == ROW_ITER || MODE == ROW_INIT;
   if (a.state && a.state->halted) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int team = threadIdx.x / TPF;
   const int t = threadIdx.x % TPF;
   T* lre = reinterpret_cast<T*>(smem_raw) + team * 2 * LS;
   T* lim = lre + LS;
-  const int p = blockIdx.x * TEAMS + team;
+  const int p = xcd_remap(blockIdx.x, gridDim.x) * TEAMS + team;
   const int ra = 2 * p, rb = 2 * p + 1;
-  const long P = a.pitch;
   cx<T>* __restrict__ spec = a.spec;
   const cx<T>* __restrict__ tw = a.tw;
   const Mat<T> m = make_mat<T>(a.prm);
-  const long NPX = (long)L * L;
+  constexpr unsigned NPX = (unsigned)L * L;
 
   cx<T> za[RMAX], zb[RMAX], zc[RMAX];
-  double acc[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) acc[i] = 0.0;
 
-  if constexpr (MODE == ROW_ITER || MODE == ROW_INV) {
-    // Hermitian-extended load of the two row spectra, pattern A.
+  if constexpr (LOADS_SPEC) {
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
       const int mm = t + TPF * s;
-      const bool direct = mm < H;
-      const int mi = direct ? mm : L - mm;
-      const cx<T>* qa = spec + ((long)ra * P + mi) * 3;
-      const cx<T>* qb = spec + ((long)rb * P + mi) * 3;
-      cx<T> a0 = qa[0], a1 = qa[1], a2 = qa[2];
-      cx<T> b0 = qb[0], b1 = qb[1], b2 = qb[2];
-      if (mi == 0 || mi == L / 2) {
-        a0.im = a1.im = a2.im = b0.im = b1.im = b2.im = (T)0;
-      }
-      if (!direct) {
-        a0 = cconj(a0); a1 = cconj(a1); a2 = cconj(a2);
-        b0 = cconj(b0); b1 = cconj(b1); b2 = cconj(b2);
-      }
+      const cx<T> a0 = load_bin<T, L, WT>(spec, mm, ra, 0), a1 = load_bin<T, L, WT>(spec, mm, ra, 1);
+      const cx<T> a2 = load_bin<T, L, WT>(spec, mm, ra, 2);
+      const cx<T> b0 = load_bin<T, L, WT>(spec, mm, rb, 0), b1 = load_bin<T, L, WT>(spec, mm, rb, 1);
+      const cx<T> b2 = load_bin<T, L, WT>(spec, mm, rb, 2);
       za[s] = {a0.re - a1.im, a0.im + a1.re};
       zb[s] = {b0.re - b1.im, b0.im + b1.re};
       zc[s] = {a2.re - b2.im, a2.im + b2.re};
       if ((s & (LOAD_GROUP - 1)) == LOAD_GROUP - 1) __builtin_amdgcn_sched_barrier(0);
     }
+    fence(za); fence(zb); fence(zc);
     fft<+1, T, L, RMAX>(za, lre, lim, t, tw);
     fft<+1, T, L, RMAX>(zb, lre, lim, t, tw);
     fft<+1, T, L, RMAX>(zc, lre, lim, t, tw);
+    fence(za); fence(zb); fence(zc);
   }
 
   if constexpr (MODE == ROW_INV) {
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
       const int x1 = t + TPF * s;
-      const long ia = (long)ra * L + x1, ib = (long)rb * L + x1;
+      const unsigned ia = (unsigned)ra * L + x1, ib = (unsigned)rb * L + x1;
       a.real_out[ia] = za[s].re; a.real_out[NPX + ia] = za[s].im; a.real_out[2 * NPX + ia] = zc[s].re;
       a.real_out[ib] = zb[s].re; a.real_out[NPX + ib] = zb[s].im; a.real_out[2 * NPX + ib] = zc[s].im;
     }
+    return;
+  }
+
+  if constexpr (MODE == ROW_EMIT) {
+    // the stored row spectra hold the forward row transforms of tau
+    const T invL = (T)(1.0 / L);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < RMAX; ++s) {
+      const int x1 = t + TPF * s;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
+        const bool isv = a.mask[ix] != 0;
+        T tau[3];
+        if (half == 0) { tau[0] = za[s].re * invL; tau[1] = za[s].im * invL; tau[2] = zc[s].re * invL; }
+        else { tau[0] = zb[s].re * invL; tau[1] = zb[s].im * invL; tau[2] = zc[s].im * invL; }
+        T sg[4] = {a.sig[ix], a.sig[NPX + ix], a.sig[2 * NPX + ix], a.sig[3 * NPX + ix]};
+        T en[4];
+        strain_from(sg, tau, isv, m, en);
+        T dummy[4];
+        const bool pl = !isv && hencky(en, dummy, m);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += (double)en[c];
+        if (a.sig_out) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) a.sig_out[c * NPX + ix] = sg[c];
+        }
+        if (a.eps_out) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) a.eps_out[c * NPX + ix] = en[c];
+        }
+        if (a.plastic_out) a.plastic_out[ix] = pl ? 1 : 0;
+      }
+    }
+    block_reduce_store<4>(acc, a.partials + (size_t)blockIdx.x * 4);
     return;
   }
 
@@ -238,48 +360,55 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
       const int x1 = t + TPF * s;
-      const long ia = (long)ra * L + x1, ib = (long)rb * L + x1;
+      const unsigned ia = (unsigned)ra * L + x1, ib = (unsigned)rb * L + x1;
       za[s] = {a.real_in[ia], a.real_in[NPX + ia]};
       zb[s] = {a.real_in[ib], a.real_in[NPX + ib]};
       zc[s] = {a.real_in[2 * NPX + ia], a.real_in[2 * NPX + ib]};
     }
-  } else {
-    // ROW_ITER or ROW_INIT: pointwise step per pixel.  The strain and mask
-    // of the next pixel pair are fetched while the current one is solved,
-    // and a scheduling fence per pixel pair bounds register pressure.
-    T* __restrict__ eps = a.eps;
+  }
+
+  if constexpr (POINTWISE) {
+    // Pointwise step per pixel.  The stress and mask of the next pixel pair
+    // are fetched while the current one is solved.  Per-thread partial sums
+    // (sigma 11, 22, 33, 12 and |e - eps|^2) are kept in LDS rather than
+    // registers, which keeps the kernel free of spills; block and global
+    // sums are FP64.
+    __shared__ T lacc[5][BS];
+    T* __restrict__ sig = a.sig;
     const uint8_t* __restrict__ vm = a.mask;
     const T E0 = (T)a.E[0], E1 = (T)a.E[1], E2 = (T)a.E[2];
-    T eo_n[2][4];
+    T so_n[2][4];
     uint8_t mk_n[2];
     auto fetch = [&](int s) {
       const int x1 = t + TPF * s;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
-        const long ix = (long)(half ? rb : ra) * L + x1;
+        const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
         mk_n[half] = vm[ix];
         if constexpr (MODE == ROW_ITER) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) eo_n[half][c] = eps[c * NPX + ix];
+          for (int c = 0; c < 4; ++c) so_n[half][c] = sig[c * NPX + ix];
         }
       }
     };
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lacc[i][threadIdx.x] = (T)0;
     fetch(0);
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
       const int x1 = t + TPF * s;
-      T eo_c[2][4];
+      T so_c[2][4];
       uint8_t mk_c[2];
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         mk_c[half] = mk_n[half];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) eo_c[half][c] = eo_n[half][c];
+        for (int c = 0; c < 4; ++c) so_c[half][c] = so_n[half][c];
       }
       if (s + 1 < RMAX) fetch(s + 1);
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
-        const long ix = (long)(half ? rb : ra) * L + x1;
+        const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
         const bool isv = mk_c[half] != 0;
         T e[3], en[4], sg[4], tau[3];
         if constexpr (MODE == ROW_INIT) {
@@ -297,42 +426,39 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
         } else {
           if (half == 0) { e[0] = za[s].re; e[1] = za[s].im; e[2] = zc[s].re; }
           else { e[0] = zb[s].re; e[1] = zb[s].im; e[2] = zc[s].im; }
-          alm_point(e, eo_c[half], isv, m, en, sg, tau);
+          alm_point(e, so_c[half], isv, m, en, sg, tau);
         }
-        eps[ix] = en[0]; eps[NPX + ix] = en[1]; eps[2 * NPX + ix] = en[2]; eps[3 * NPX + ix] = en[3];
-        acc[0] += (double)sg[0]; acc[1] += (double)sg[1]; acc[2] += (double)sg[2]; acc[3] += (double)sg[3];
-        acc[4] += (double)en[0]; acc[5] += (double)en[1]; acc[6] += (double)en[2]; acc[7] += (double)en[3];
-        const double c0 = (double)e[0] - (double)en[0], c1 = (double)e[1] - (double)en[1];
-        const double c2 = (double)en[2], c3 = (double)e[2] - (double)en[3];
-        acc[8] += c0 * c0 + c1 * c1 + c2 * c2 + 2.0 * c3 * c3;
+        sig[ix] = sg[0]; sig[NPX + ix] = sg[1]; sig[2 * NPX + ix] = sg[2]; sig[3 * NPX + ix] = sg[3];
+        {
+          const T c0 = e[0] - en[0], c1 = e[1] - en[1], c2 = en[2], c3 = e[2] - en[3];
+          const T v5[5] = {sg[0], sg[1], sg[2], sg[3], c0 * c0 + c1 * c1 + c2 * c2 + (T)2 * c3 * c3};
+#pragma unroll
+          for (int i = 0; i < 5; ++i) lacc[i][threadIdx.x] += v5[i];
+        }
         if (half == 0) { za[s] = {tau[0], tau[1]}; zc[s].re = tau[2]; }
         else { zb[s] = {tau[0], tau[1]}; zc[s].im = tau[2]; }
       }
       __builtin_amdgcn_sched_barrier(0);
     }
+    fence(za); fence(zb); fence(zc);
+    double accd[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) accd[i] = (double)lacc[i][threadIdx.x];
+    block_reduce_store<5>(accd, a.partials + (size_t)blockIdx.x * NPART);
   }
 
   fft<-1, T, L, RMAX>(za, lre, lim, t, tw);
   fft<-1, T, L, RMAX>(zb, lre, lim, t, tw);
   fft<-1, T, L, RMAX>(zc, lre, lim, t, tw);
 
-  // Split each complex transform into the two real-signal half spectra:
-  // X = (Z[m] + conj Z[L-m]) / 2, Y = (Z[m] - conj Z[L-m]) / (2i).
   // Za -> (11, 22) of row a, Zb -> (11, 22) of row b, Zc -> 12 of rows a, b.
-  split_store<T, L, RMAX>(za, lre, lim, t, spec + (long)ra * P * 3, 0, spec + (long)ra * P * 3, 1);
-  split_store<T, L, RMAX>(zb, lre, lim, t, spec + (long)rb * P * 3, 0, spec + (long)rb * P * 3, 1);
-  split_store<T, L, RMAX>(zc, lre, lim, t, spec + (long)ra * P * 3, 2, spec + (long)rb * P * 3, 2);
-
-  if constexpr (MODE == ROW_ITER || MODE == ROW_INIT) {
-    // teams of one block reduce together; per-block partials in fixed order
-    block_reduce_store<9>(acc, a.partials + (long)blockIdx.x * NPART);
-  }
+  split_store<T, L, RMAX, WT>(za, lre, lim, t, spec, ra, 0, ra, 1);
+  split_store<T, L, RMAX, WT>(zb, lre, lim, t, spec, rb, 0, rb, 1);
+  split_store<T, L, RMAX, WT>(zc, lre, lim, t, spec, ra, 2, rb, 2);
 }
 
 // ---------------------------------------------------------------------------
-// Column pass.  A team of TPF threads owns one column m1 of the row spectra;
-// W adjacent columns per block with the column index fastest across lanes so
-// each row access covers W * 3 complex contiguous values.
+// Column pass.
 template <typename T>
 __device__ __forceinline__ void green_apply(cx<T>* tt, cx<T> k1, cx<T> k2, const T lam0, const T mu0,
                                             const T scale) {
@@ -362,18 +488,33 @@ __device__ __forceinline__ void green_apply(cx<T>* tt, cx<T> k1, cx<T> k2, const
   tt[2] = {(T)-0.5 * e12.re, (T)-0.5 * e12.im};
 }
 
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous range of logical column groups so neighbouring groups, which
-  // share cache lines, meet in the same L2.
-  const int x = b & 7, q = nb >> 3, r = nb & 7;
-  return x * q + (x < r ? x : r) + (b >> 3);
+// Green tensor at momentum (m1, m2), or E at q = 0.
+template <typename T>
+__device__ __forceinline__ void green_at(cx<T>* tt, int m1, int m2, const ColArgs<T>& a, const T lam0, const T mu0,
+                                         const T scale) {
+  if (m1 == 0 && m2 == 0) {
+    double E0 = a.E[0], E1 = a.E[1], E2 = a.E[2];
+    if (a.state) { E0 = a.state->E[0]; E1 = a.state->E[1]; E2 = a.state->E[2]; }
+    tt[0] = {(T)E0, (T)0};
+    tt[1] = {(T)E1, (T)0};
+    tt[2] = {(T)E2, (T)0};
+    return;
+  }
+  cx<T> k1 = a.ktab[m1], k2 = a.ktab[m2];
+  if (a.flip1) k1 = {-k1.re, k1.im};   // k(-q) = -conj(k(q))
+  if (a.flip2) k2 = {-k2.re, k2.im};
+  green_apply(tt, k1, k2, lam0, mu0, scale);
 }
 
+// A team of TPF threads owns one column m1 of the packed row spectra; a
+// block owns one tile of W adjacent columns (contiguous in memory), with the
+// column index fastest across lanes.  Column 0 carries the real bins
+// m1 = 0 (real part) and m1 = L/2 (imaginary part): its transform is split
+// with conj-symmetry into the two real-signal spectra, each gets its own
+// Green tensor, and the results are packed again before the inverse.
 template <typename T, int L, int RMAX, int W, int MODE>
-__global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(2))) k_column(ColArgs<T> a) {
+__global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_COL_WPE))) k_column(ColArgs<T> a) {
   constexpr int TPF = L / RMAX;
-  constexpr int H = L / 2 + 1;
   constexpr int LS = LdsSize<L>::value;
   if (a.state && a.state->halted) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -383,21 +524,17 @@ __global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_
   T* lim = lre + LS;
   const int g = xcd_remap(blockIdx.x, gridDim.x);
   const int m1 = g * W + w;
-  const bool valid = m1 < H;
-  const long P = a.pitch;
+  const bool packed = (g == 0);           // block-uniform: tile 0 holds column 0
   cx<T>* __restrict__ spec = a.spec;
   const cx<T>* __restrict__ tw = a.tw;
+  cx<T>* __restrict__ tile = spec + (size_t)g * L * W * 3;
 
   cx<T> v[3][RMAX];
 #pragma unroll
   for (int s = 0; s < RMAX; ++s) {
     const int m2 = t + TPF * s;
-    if (valid) {
-      const cx<T>* q = spec + ((long)m2 * P + m1) * 3;
-      v[0][s] = q[0]; v[1][s] = q[1]; v[2][s] = q[2];
-    } else {
-      v[0][s] = v[1][s] = v[2][s] = {(T)0, (T)0};
-    }
+    const cx<T>* q = tile + ((unsigned)m2 * W + w) * 3u;
+    v[0][s] = q[0]; v[1][s] = q[1]; v[2][s] = q[2];
   }
   if constexpr ((MODE & COL_FWD) != 0) {
 #pragma unroll
@@ -405,52 +542,81 @@ __global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_
   }
   if constexpr ((MODE & COL_GREEN) != 0) {
     const T lam0 = (T)a.lam0, mu0 = (T)a.mu0, scale = (T)a.scale;
-    cx<T> k1 = valid ? a.ktab[m1] : cx<T>{(T)0, (T)0};
-    if (a.flip1) k1 = {-k1.re, k1.im};   // k(-q) = -conj(k(q))
+    if (packed) {
+      // Column 0 (bins m1 = 0 and L/2 packed) passes its transform through a
+      // small global buffer to read the partners conj Z[L - m2]; the branch is
+      // uniform over the block, and the barrier orders the global writes
+      // before the reads within the block.
+      if (w == 0) {
 #pragma unroll
-    for (int s = 0; s < RMAX; ++s) {
-      const int m2 = t + TPF * s;
-      cx<T> k2 = a.ktab[m2];
-      if (a.flip2) k2 = {-k2.re, k2.im};
-      cx<T> tt[3] = {v[0][s], v[1][s], v[2][s]};
-      if (m1 == 0 && m2 == 0) {
-        tt[0] = {(T)a.E[0], (T)0};
-        tt[1] = {(T)a.E[1], (T)0};
-        tt[2] = {(T)a.E[2], (T)0};
-        if (a.state) {
-          tt[0].re = (T)a.state->E[0]; tt[1].re = (T)a.state->E[1]; tt[2].re = (T)a.state->E[2];
-        }
-      } else {
-        green_apply(tt, k1, k2, lam0, mu0, scale);
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int s = 0; s < RMAX; ++s) a.xbuf[c * L + t + TPF * s] = v[c][s];
       }
-      v[0][s] = tt[0]; v[1][s] = tt[1]; v[2][s] = tt[2];
+      __threadfence_block();
+      __syncthreads();
+      if (w == 0) {
+#pragma unroll
+        for (int s = 0; s < RMAX; ++s) {
+          const int m2 = t + TPF * s;
+          const int mr = (L - m2) & (L - 1);
+          cx<T> x0[3], xn[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const cx<T> zr = cconj(a.xbuf[c * L + mr]);
+            const cx<T> d = v[c][s] - zr;
+            x0[c] = cscale(v[c][s] + zr, (T)0.5);
+            xn[c] = {d.im * (T)0.5, -d.re * (T)0.5};
+          }
+          green_at(x0, 0, m2, a, lam0, mu0, scale);
+          green_at(xn, L / 2, m2, a, lam0, mu0, scale);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[c][s] = {x0[c].re - xn[c].im, x0[c].im + xn[c].re};
+        }
+      }
+    }
+    if (!packed || w != 0) {
+#pragma unroll
+      for (int s = 0; s < RMAX; ++s) {
+        const int m2 = t + TPF * s;
+        cx<T> tt[3] = {v[0][s], v[1][s], v[2][s]};
+        green_at(tt, m1, m2, a, lam0, mu0, scale);
+        v[0][s] = tt[0]; v[1][s] = tt[1]; v[2][s] = tt[2];
+      }
     }
   }
   if constexpr ((MODE & COL_INV) != 0) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) fft<+1, T, L, RMAX>(v[c], lre, lim, t, tw);
   }
-  if (valid) {
 #pragma unroll
-    for (int s = 0; s < RMAX; ++s) {
-      const int m2 = t + TPF * s;
-      cx<T>* q = spec + ((long)m2 * P + m1) * 3;
-      q[0] = v[0][s]; q[1] = v[1][s]; q[2] = v[2][s];
-    }
+  for (int s = 0; s < RMAX; ++s) {
+    const int m2 = t + TPF * s;
+    cx<T>* q = tile + ((unsigned)m2 * W + w) * 3u;
+    q[0] = v[0][s]; q[1] = v[1][s]; q[2] = v[2][s];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Launch configuration per (precision, L).
+// Launch configuration per (precision, L).  The column tile width W is also
+// the spectrum's tile width.
 template <typename T, int L>
 struct Cfg {
-  static constexpr int RBASE = (L < 8 || sizeof(T) == 8) ? 4 : 8;
-  static constexpr int RMAX = RBASE * 1024 >= L ? RBASE : L / 1024;   // at most 1024 threads per transform
+  // Row pass.
+  static constexpr int RBASE = L < 8 ? 4 : (sizeof(T) == 8 ? PM_ROW_R64 : PM_ROW_R32);
+  static constexpr int RB = RBASE > L ? L : RBASE;
+  static constexpr int RMAX = RB * PM_ROW_TPF_MAX >= L ? RB : L / PM_ROW_TPF_MAX;
   static constexpr int TPF = L / RMAX;
   static constexpr int ROW_TEAMS_RAW = TPF >= 256 ? 1 : 256 / TPF;
   static constexpr int ROW_TEAMS = ROW_TEAMS_RAW > L / 2 ? L / 2 : ROW_TEAMS_RAW;
-  static constexpr int COL_W_RAW = TPF >= 256 ? (sizeof(T) == 8 ? 2 : 4) : (256 / TPF > 16 ? 16 : 256 / TPF);
-  static constexpr int COL_W = COL_W_RAW * TPF > 1024 ? 1024 / TPF : COL_W_RAW;
+  // Column pass: larger radix for long columns, blocks of at most 512 threads.
+  static constexpr int CBASE = L < 8 ? 4 : (sizeof(T) == 8 ? (L >= 2048 ? PM_COL_R64 : 4) : (L >= 2048 ? PM_COL_R32 : 8));
+  static constexpr int CB = CBASE > L ? L : CBASE;
+  static constexpr int COL_RMAX = CB * 512 >= L ? CB : L / 512;
+  static constexpr int COL_TPF = L / COL_RMAX;
+  static constexpr int COL_W_RAW = COL_TPF >= 256 ? (sizeof(T) == 8 ? 1 : PM_COL_W32) : (256 / COL_TPF > 16 ? 16 : 256 / COL_TPF);
+  static constexpr int COL_W_CAP = COL_W_RAW * COL_TPF > 1024 ? (1024 / COL_TPF > 0 ? 1024 / COL_TPF : 1) : COL_W_RAW;
+  static constexpr int COL_W = COL_W_CAP > L / 2 ? L / 2 : COL_W_CAP;
 };
 
 template <typename T, int L>
@@ -465,7 +631,7 @@ static size_t col_lds() {
 template <typename T, int L, int MODE>
 static hipError_t launch_row_LM(const RowArgs<T>& a, hipStream_t st) {
   using C = Cfg<T, L>;
-  auto kern = k_row<T, L, C::RMAX, C::ROW_TEAMS, MODE>;
+  auto kern = k_row<T, L, C::RMAX, C::ROW_TEAMS, C::COL_W, MODE>;
   static bool attr = false;
   const size_t lds = row_lds<T, L>();
   if (!attr) {
@@ -481,7 +647,7 @@ static hipError_t launch_row_LM(const RowArgs<T>& a, hipStream_t st) {
 template <typename T, int L, int MODE>
 static hipError_t launch_col_LM(const ColArgs<T>& a, hipStream_t st) {
   using C = Cfg<T, L>;
-  auto kern = k_column<T, L, C::RMAX, C::COL_W, MODE>;
+  auto kern = k_column<T, L, C::COL_RMAX, C::COL_W, MODE>;
   static bool attr = false;
   const size_t lds = col_lds<T, L>();
   if (!attr) {
@@ -489,9 +655,8 @@ static hipError_t launch_col_LM(const ColArgs<T>& a, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const int H = L / 2 + 1;
-  const int grid = (H + C::COL_W - 1) / C::COL_W;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::COL_W * C::TPF), lds, st, a);
+  const int grid = (L / 2) / C::COL_W;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::COL_W * C::COL_TPF), lds, st, a);
   return hipGetLastError();
 }
 
@@ -502,6 +667,7 @@ static hipError_t launch_row_L(const RowArgs<T>& a, hipStream_t st) {
     case ROW_INIT: return launch_row_LM<T, L, ROW_INIT>(a, st);
     case ROW_FWD: return launch_row_LM<T, L, ROW_FWD>(a, st);
     case ROW_INV: return launch_row_LM<T, L, ROW_INV>(a, st);
+    case ROW_EMIT: return launch_row_LM<T, L, ROW_EMIT>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -516,6 +682,11 @@ static hipError_t launch_col_L(const ColArgs<T>& a, hipStream_t st) {
     default: return hipErrorInvalidValue;
   }
 }
+
+template <typename T, int L>
+static int row_grid_L() { return (L / 2) / Cfg<T, L>::ROW_TEAMS; }
+template <typename T, int L>
+static int tile_w_L() { return Cfg<T, L>::COL_W; }
 
 #define PM_DISPATCH_L(FN, T, L, ...)            \
   switch (L) {                                  \
@@ -543,25 +714,30 @@ hipError_t launch_col(int L, const ColArgs<T>& a, hipStream_t st) {
   PM_DISPATCH_L(launch_col_L, T, L, a, st)
 }
 
-template <typename T, int L>
-static int row_grid_L() { return (L / 2) / Cfg<T, L>::ROW_TEAMS; }
+#define PM_DISPATCH_INT(FN, T, L)     \
+  switch (L) {                        \
+    case 4: return FN<T, 4>();        \
+    case 8: return FN<T, 8>();        \
+    case 16: return FN<T, 16>();      \
+    case 32: return FN<T, 32>();      \
+    case 64: return FN<T, 64>();      \
+    case 128: return FN<T, 128>();    \
+    case 256: return FN<T, 256>();    \
+    case 512: return FN<T, 512>();    \
+    case 1024: return FN<T, 1024>();  \
+    case 2048: return FN<T, 2048>();  \
+    case 4096: return FN<T, 4096>();  \
+    case 8192: return FN<T, 8192>();  \
+    default: return -1;               \
+  }
+
 template <typename T>
 int row_grid(int L) {
-  switch (L) {
-    case 4: return row_grid_L<T, 4>();
-    case 8: return row_grid_L<T, 8>();
-    case 16: return row_grid_L<T, 16>();
-    case 32: return row_grid_L<T, 32>();
-    case 64: return row_grid_L<T, 64>();
-    case 128: return row_grid_L<T, 128>();
-    case 256: return row_grid_L<T, 256>();
-    case 512: return row_grid_L<T, 512>();
-    case 1024: return row_grid_L<T, 1024>();
-    case 2048: return row_grid_L<T, 2048>();
-    case 4096: return row_grid_L<T, 4096>();
-    case 8192: return row_grid_L<T, 8192>();
-    default: return -1;
-  }
+  PM_DISPATCH_INT(row_grid_L, T, L)
+}
+template <typename T>
+int tile_width(int L) {
+  PM_DISPATCH_INT(tile_w_L, T, L)
 }
 
 }  // namespace pm

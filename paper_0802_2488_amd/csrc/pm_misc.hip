@@ -12,47 +12,45 @@ __device__ __forceinline__ double norm4(const double* a) {
 __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partials, int nblk, DevState* st,
                                                 DevParams prm) {
   if (st->halted) return;
-  __shared__ double red[256][9];
-  double s[9];
+  __shared__ double red[256][5];
+  double s[5];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) s[i] = 0.0;
+  for (int i = 0; i < 5; ++i) s[i] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 256) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) s[i] += partials[(long)b * NPART + i];
+    for (int i = 0; i < 5; ++i) s[i] += partials[(long)b * NPART + i];
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) red[threadIdx.x][i] = s[i];
+  for (int i = 0; i < 5; ++i) red[threadIdx.x][i] = s[i];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) red[threadIdx.x][i] += red[threadIdx.x + off][i];
+      for (int i = 0; i < 5; ++i) red[threadIdx.x][i] += red[threadIdx.x + off][i];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     const double inv = 1.0 / prm.npx;
-    double sm[4], em[4], dsm[4];
+    double sm[4], dsm[4];
     for (int i = 0; i < 4; ++i) {
       sm[i] = red[0][i] * inv;
-      em[i] = red[0][4 + i] * inv;
       dsm[i] = sm[i] - st->sm[i];
     }
     const int it = st->iter + 1;
     st->iter = it;
     const double ns = fmax(norm4(sm), st->floor_s);
-    const double rcmp = sqrt(red[0][8] * inv) / st->normE;
+    const double rcmp = sqrt(red[0][4] * inv) / st->normE;
     const double rmac = it >= 2 ? norm4(dsm) / ns : INFINITY;
     for (int i = 0; i < 4; ++i) {
       st->sm_prev[i] = st->sm[i];
       st->sm[i] = sm[i];
-      st->em[i] = em[i];
     }
     st->res_cmp = rcmp;
     st->res_mac = rmac;
     st->res_eq = INFINITY;
     bool bad = false;
-    for (int i = 0; i < 9; ++i) bad |= !isfinite(red[0][i]);
+    for (int i = 0; i < 5; ++i) bad |= !isfinite(red[0][i]);
     if (bad) {
       st->status = ST_NAN;
       st->halted = 1;
@@ -68,37 +66,24 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
   }
 }
 
-// Backward-difference divergence of eq. 1 from sigma = S(eps) (0 on voids).
+// Backward-difference divergence of eq. 1 of the stored stress:
+// div_i(x) = sum_j sigma_ij(x) - sigma_ij(x - e^j), direction 1 = x1.
 template <typename T>
-__device__ __forceinline__ void sigma_at(const T* __restrict__ eps, const uint8_t* __restrict__ vm, long ix, long npx,
-                                         const Mat<T>& m, T* s) {
-  if (vm[ix]) {
-    s[0] = s[1] = s[2] = s[3] = (T)0;
-    return;
-  }
-  T e[4] = {eps[ix], eps[npx + ix], eps[2 * npx + ix], eps[3 * npx + ix]};
-  hencky(e, s, m);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_div(const T* __restrict__ eps, const uint8_t* __restrict__ vm,
-                                             double* __restrict__ partials, const DevState* st, DevParams prm,
-                                             int L, int force) {
+__global__ void __launch_bounds__(256) k_div(const T* __restrict__ sig, double* __restrict__ partials,
+                                             const DevState* st, int L, int force) {
   if (!force && (st->halted || !st->need_eq)) return;
-  const Mat<T> m = make_mat<T>(prm);
   const long npx = (long)L * L;
+  const T* __restrict__ s11 = sig;
+  const T* __restrict__ s22 = sig + npx;
+  const T* __restrict__ s12 = sig + 3 * npx;
   double acc[1] = {0.0};
   for (long ix = (long)blockIdx.x * blockDim.x + threadIdx.x; ix < npx; ix += (long)gridDim.x * blockDim.x) {
-    const int x1 = (int)(ix % L);
+    const int x1 = (int)(ix & (L - 1));
     const int x2 = (int)(ix / L);
-    const long i1 = (long)x2 * L + ((x1 + L - 1) % L);   // x - e^1
-    const long i2 = (long)((x2 + L - 1) % L) * L + x1;   // x - e^2
-    T s[4], s1[4], s2[4];
-    sigma_at(eps, vm, ix, npx, m, s);
-    sigma_at(eps, vm, i1, npx, m, s1);
-    sigma_at(eps, vm, i2, npx, m, s2);
-    const double d1 = ((double)s[0] - (double)s1[0]) + ((double)s[3] - (double)s2[3]);
-    const double d2 = ((double)s[3] - (double)s1[3]) + ((double)s[1] - (double)s2[1]);
+    const long i1 = (long)x2 * L + ((x1 + L - 1) & (L - 1));   // x - e^1
+    const long i2 = (long)((x2 + L - 1) & (L - 1)) * L + x1;   // x - e^2
+    const double d1 = ((double)s11[ix] - (double)s11[i1]) + ((double)s12[ix] - (double)s12[i2]);
+    const double d2 = ((double)s12[ix] - (double)s12[i1]) + ((double)s22[ix] - (double)s22[i2]);
     acc[0] += d1 * d1 + d2 * d2;
   }
   block_reduce_store<1>(acc, partials + blockIdx.x);
@@ -144,29 +129,27 @@ __global__ void k_begin(DevState* st, double E0, double E1, double E2, double fl
   }
 }
 
-// Step outputs: sigma = S(eps) (0 on voids), eps, plastic mask; also the
-// equivalent-strain yield test for the mask: matrix and 3 mu eps_eq > Y.
-template <typename T>
-__global__ void __launch_bounds__(256) k_emit(const T* __restrict__ eps, const uint8_t* __restrict__ vm,
-                                              T* __restrict__ sig_out, T* __restrict__ eps_out,
-                                              uint8_t* __restrict__ pl_out, DevParams prm, long npx) {
-  const Mat<T> m = make_mat<T>(prm);
-  for (long ix = (long)blockIdx.x * blockDim.x + threadIdx.x; ix < npx; ix += (long)gridDim.x * blockDim.x) {
-    T e[4] = {eps[ix], eps[npx + ix], eps[2 * npx + ix], eps[3 * npx + ix]};
-    T s[4];
-    bool pl = false;
-    if (vm[ix]) {
-      s[0] = s[1] = s[2] = s[3] = (T)0;
-    } else {
-      pl = hencky(e, s, m);
+// Final FP64 reduction of the per-block strain sums written by the output pass.
+__global__ void __launch_bounds__(256) k_reduce_emit(const double* __restrict__ partials, int nblk, DevState* st,
+                                                     double npx) {
+  __shared__ double red[256][4];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] += partials[(long)b * 4 + i];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[threadIdx.x][i] = s[i];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[threadIdx.x][i] += red[threadIdx.x + off][i];
     }
-    if (sig_out) {
-      sig_out[ix] = s[0]; sig_out[npx + ix] = s[1]; sig_out[2 * npx + ix] = s[2]; sig_out[3 * npx + ix] = s[3];
-    }
-    if (eps_out) {
-      eps_out[ix] = e[0]; eps_out[npx + ix] = e[1]; eps_out[2 * npx + ix] = e[2]; eps_out[3 * npx + ix] = e[3];
-    }
-    if (pl_out) pl_out[ix] = pl ? 1 : 0;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 4; ++i) st->em[i] = red[0][i] / npx;
   }
 }
 
@@ -200,38 +183,27 @@ hipError_t launch_reduce(const double* partials, int nblk, DevState* st, const D
 }
 
 template <typename T>
-hipError_t launch_div(const T* eps, const uint8_t* mask, double* partials, DevState* st, const DevParams& prm, int L,
-                      int force, hipStream_t s) {
+hipError_t launch_div(const T* sig, double* partials, DevState* st, const DevParams& prm, int L, int force,
+                      hipStream_t s) {
   const int g = div_grid(L);
-  hipLaunchKernelGGL(k_div<T>, dim3(g), dim3(256), 0, s, eps, mask, partials, st, prm, L, force);
+  hipLaunchKernelGGL(k_div<T>, dim3(g), dim3(256), 0, s, sig, partials, st, L, force);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_div, dim3(1), dim3(256), 0, s, partials, g, st, prm, force);
   return hipGetLastError();
 }
-template hipError_t launch_div<float>(const float*, const uint8_t*, double*, DevState*, const DevParams&, int, int,
-                                      hipStream_t);
-template hipError_t launch_div<double>(const double*, const uint8_t*, double*, DevState*, const DevParams&, int, int,
-                                       hipStream_t);
+template hipError_t launch_div<float>(const float*, double*, DevState*, const DevParams&, int, int, hipStream_t);
+template hipError_t launch_div<double>(const double*, double*, DevState*, const DevParams&, int, int, hipStream_t);
 
 hipError_t launch_begin(DevState* st, const double* E, double floor_s, hipStream_t s) {
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, st, E[0], E[1], E[2], floor_s);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_emit(const T* eps, const uint8_t* mask, T* sig, T* eps_out, uint8_t* pl, const DevParams& prm,
-                       int L, hipStream_t s) {
-  const long npx = (long)L * L;
-  long g = (npx + 255) / 256;
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_emit<T>, dim3((int)g), dim3(256), 0, s, eps, mask, sig, eps_out, pl, prm, npx);
+hipError_t launch_reduce_emit(const double* partials, int nblk, DevState* st, double npx, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_emit, dim3(1), dim3(256), 0, s, partials, nblk, st, npx);
   return hipGetLastError();
 }
-template hipError_t launch_emit<float>(const float*, const uint8_t*, float*, float*, uint8_t*, const DevParams&, int,
-                                       hipStream_t);
-template hipError_t launch_emit<double>(const double*, const uint8_t*, double*, double*, uint8_t*, const DevParams&,
-                                        int, hipStream_t);
 
 hipError_t launch_mask(uint8_t* out, long npx, double f, uint64_t seed, hipStream_t s) {
   long g = (npx + 255) / 256;

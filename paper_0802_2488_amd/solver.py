@@ -115,20 +115,23 @@ class Solver:
 
     # -- kernel-level hooks -------------------------------------------------
     def buffers(self):
-        """(eps state tensor (4, L, L), spectrum tensor (L, pitch, 3, 2)) views of the workspace."""
+        """Views of the workspace: eps state (4, L, L) and the raw half
+        spectrum (L*L/2*3*2,) in the tiled layout of pm_spectrum_tile."""
         e = ctypes.c_void_p()
         s = ctypes.c_void_p()
         check(lib().pm_solver_buffers(self.handle, ctypes.byref(e), ctypes.byref(s)), "pm_solver_buffers")
         L = self.L
-        P = lib().pm_spectrum_pitch(L)
         es = 8 if self.dtype == torch.float64 else 4
         base = self.workspace.data_ptr()
         eo = (e.value - base) // es
         so = (s.value - base) // es
         flat = self.workspace.view(self.dtype)
         eps_t = flat[eo: eo + 4 * L * L].view(4, L, L)
-        spec_t = flat[so: so + L * P * 6].view(L, P, 3, 2)
+        spec_t = flat[so: so + L * (L // 2) * 6]
         return eps_t, spec_t
+
+    def tile(self) -> int:
+        return lib().pm_spectrum_tile(self.L, self.params.precision)
 
     def debug_forward(self, real3: torch.Tensor):
         check(lib().pm_debug_forward(self.handle, real3.contiguous().data_ptr()), "pm_debug_forward")

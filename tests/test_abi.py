@@ -45,13 +45,16 @@ def test_workspace_bytes_and_validation():
         assert b"" != L.pm_last_error()
 
 
-def test_status_strings_and_pitch():
+def test_status_strings_and_tile():
     L = _lib.lib()
     assert L.pm_status_string(0) == b"ok"
     assert L.pm_status_string(-4).startswith(b"not converged")
-    for n in (4, 64, 4096):
-        P = L.pm_spectrum_pitch(n)
-        assert P >= n // 2 + 1 and P % 16 == 0
+    for n in (4, 64, 4096, 8192):
+        for prec in (0, 1):
+            WT = L.pm_spectrum_tile(n, prec)
+            assert WT >= 1 and (n // 2) % WT == 0
+    assert L.pm_spectrum_tile(48, 0) < 0
+    assert L.pm_spectrum_tile(64, 3) < 0
 
 
 def test_create_rejects_bad_arguments_without_touching_the_device():

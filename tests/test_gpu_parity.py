@@ -53,10 +53,35 @@ def _solver(L, precision, **kw):
     return pms.Solver(torch.zeros((L, L), dtype=torch.uint8, device="cuda"), gpu_params(L, precision, **kw))
 
 
-def _spec_to_complex(spec, L):
-    """(L, P, 3, 2) device view -> complex (L, L//2+1, 3) numpy."""
-    s = spec.detach().cpu().double().numpy()[:, : L // 2 + 1]
-    return s[..., 0] + 1j * s[..., 1]
+def unpack_spec(flat, L, WT):
+    """Tiled packed half spectrum (after a column transform) -> (L, L//2+1, 3)."""
+    a = flat.detach().cpu().double().numpy().reshape(L // 2 // WT, L, WT, 3, 2)
+    z = (a[..., 0] + 1j * a[..., 1]).transpose(1, 0, 2, 3).reshape(L, L // 2, 3)
+    out = np.zeros((L, L // 2 + 1, 3), complex)
+    out[:, 1: L // 2] = z[:, 1:]
+    Z0 = z[:, 0]
+    Zr = np.conj(Z0[(-np.arange(L)) % L])
+    out[:, 0] = (Z0 + Zr) / 2
+    out[:, L // 2] = (Z0 - Zr) / 2j
+    return out
+
+
+def pack_spec(full, L, WT):
+    """(L, L//2+1, 3) column-transformed half spectrum -> flat tiled packed layout."""
+    z = np.empty((L, L // 2, 3), complex)
+    z[:, 1:] = full[:, 1: L // 2]
+    z[:, 0] = full[:, 0] + 1j * full[:, L // 2]
+    t = z.reshape(L, L // 2 // WT, WT, 3).transpose(1, 0, 2, 3)
+    return np.stack([t.real, t.imag], axis=-1).reshape(-1)
+
+
+def test_layout_helpers_roundtrip():
+    L, WT = 16, 2
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(L, L, 3))
+    full = np.fft.rfft2(x, axes=(0, 1))
+    flat = torch.tensor(pack_spec(full, L, WT))
+    np.testing.assert_allclose(unpack_spec(flat, L, WT), full, atol=1e-12)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
@@ -68,7 +93,7 @@ def test_fft_forward_matches_numpy(L, precision, tol):
     xt = torch.tensor(x, dtype=s.dtype, device="cuda")
     s.debug_forward(xt)
     _, spec = s.buffers()
-    got = _spec_to_complex(spec, L)
+    got = unpack_spec(spec, L, s.tile())
     ref = np.moveaxis(np.fft.rfft2(x, axes=(1, 2)), 0, -1)
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
@@ -79,13 +104,9 @@ def test_fft_inverse_matches_numpy(L, precision, tol):
     s = _solver(L, precision)
     rng = np.random.default_rng(L + 1)
     x = rng.normal(size=(3, L, L))
-    X = np.fft.rfft2(x, axes=(1, 2))                     # Hermitian half spectrum
+    X = np.moveaxis(np.fft.rfft2(x, axes=(1, 2)), 0, -1)       # Hermitian half spectrum
     _, spec = s.buffers()
-    P = spec.shape[1]
-    buf = np.zeros((L, P, 3, 2))
-    buf[:, : L // 2 + 1, :, 0] = np.moveaxis(X, 0, -1).real
-    buf[:, : L // 2 + 1, :, 1] = np.moveaxis(X, 0, -1).imag
-    spec.copy_(torch.tensor(buf, dtype=s.dtype, device="cuda"))
+    spec.copy_(torch.tensor(pack_spec(X, L, s.tile()), dtype=s.dtype, device="cuda"))
     out = torch.empty((3, L, L), dtype=s.dtype, device="cuda")
     s.debug_inverse(out)
     got = out.cpu().double().numpy()
@@ -99,22 +120,32 @@ def test_green_kernel_matches_oracle(L, variant):
     s = _solver(L, "fp64", variant=variant)
     rng = np.random.default_rng(7 + L)
     _, spec = s.buffers()
-    P = spec.shape[1]
-    t = rng.normal(size=(L, L // 2 + 1, 3)) + 1j * rng.normal(size=(L, L // 2 + 1, 3))
-    buf = np.zeros((L, P, 3, 2))
-    buf[:, : L // 2 + 1, :, 0] = t.real
-    buf[:, : L // 2 + 1, :, 1] = t.imag
-    spec.copy_(torch.tensor(buf, device="cuda"))
+    WT = s.tile()
+    # random packed spectrum: columns 1..L/2-1 as they are, column 0 packed
+    z = rng.normal(size=(L, L // 2, 3)) + 1j * rng.normal(size=(L, L // 2, 3))
+    t = z.reshape(L, L // 2 // WT, WT, 3).transpose(1, 0, 2, 3)
+    spec.copy_(torch.tensor(np.stack([t.real, t.imag], axis=-1).reshape(-1), device="cuda"))
     E = (0.3, -0.2, 0.1)
     s.debug_green(E)
-    got = _spec_to_complex(spec, L)
-    tau = np.empty((L, L // 2 + 1, 2, 2), complex)
-    tau[..., 0, 0], tau[..., 1, 1] = t[..., 0], t[..., 1]
-    tau[..., 0, 1] = tau[..., 1, 0] = t[..., 2]
+    a = spec.cpu().numpy().reshape(L // 2 // WT, L, WT, 3, 2)
+    got = (a[..., 0] + 1j * a[..., 1]).transpose(1, 0, 2, 3).reshape(L, L // 2, 3)
     G = dg.green_on_grid(L, 4.0, 2.0, variant)
-    e = dg.apply_green(G, tau)
-    ref = np.stack([e[..., 0, 0], e[..., 1, 1], e[..., 0, 1]], axis=-1)
-    ref[0, 0] = E
+
+    def apply(Gq, v):
+        tau = np.empty(v.shape[:-1] + (2, 2), complex)
+        tau[..., 0, 0], tau[..., 1, 1] = v[..., 0], v[..., 1]
+        tau[..., 0, 1] = tau[..., 1, 0] = v[..., 2]
+        e = dg.apply_green(Gq, tau)
+        return np.stack([e[..., 0, 0], e[..., 1, 1], e[..., 0, 1]], axis=-1)
+
+    ref = np.empty_like(got)
+    ref[:, 1:] = apply(G[:, 1: L // 2], z[:, 1:])
+    Z0 = z[:, 0]
+    Zr = np.conj(Z0[(-np.arange(L)) % L])
+    e0 = apply(G[:, 0], (Z0 + Zr) / 2)
+    e0[0] = E
+    eN = apply(G[:, L // 2], (Z0 - Zr) / 2j)
+    ref[:, 0] = e0 + 1j * eN
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
