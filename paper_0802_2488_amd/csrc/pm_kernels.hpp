@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "pm_fft.hpp"
 #include "pm_internal.h"
 
@@ -33,6 +35,9 @@
 #endif
 #ifndef PM_ROW_WPE
 #define PM_ROW_WPE 2          // minimum waves per SIMD requested for the row pass
+#endif
+#ifndef PM_ROW_PREFETCH
+#define PM_ROW_PREFETCH 2     // pixel pairs of stress fetched ahead in the row pass
 #endif
 #ifndef PM_COL_R32
 #define PM_COL_R32 16         // column-pass radix, FP32, L >= 2048
@@ -212,12 +217,31 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// Whether a row pair's spectrum slice is staged through LDS: FFT buffers,
+// the stage (3 L complex per team), the per-thread sums and the reduction
+// scratch must fit in the 160 KiB of LDS of a CU.
+template <typename T, int L, int TEAMS, int TPF>
+struct RowStage {
+  static constexpr size_t bytes = (size_t)TEAMS * 2 * LdsSize<L>::value * sizeof(T) +
+                                  (size_t)TEAMS * 3 * L * 2 * sizeof(T) + 5 * (size_t)TEAMS * TPF * sizeof(T) + 16 * 5 * 8;
+  static constexpr bool value = bytes <= 150 * 1024;
+};
+
+// A row pair's view of the half spectrum: bins m1 of rows (ra + r), r = 0, 1,
+// at base + (m1 / WT) * TSTRIDE + r * WT * 3 + (m1 % WT) * 3 + c.  The same
+// accessor addresses the spectrum in HBM (base at row ra, TSTRIDE = L WT 3)
+// and a row pair's copy staged in LDS (TSTRIDE = 2 WT 3).
+template <int WT, int TSTRIDE>
+__device__ __forceinline__ unsigned pidx(int m1, int r, int c) {
+  return (unsigned)(m1 / WT) * TSTRIDE + (unsigned)(r * WT * 3 + (m1 % WT) * 3 + c);
+}
+
 // Row-pass output: split the complex transform Z of x + i y into the half
-// spectra X (component cxi of row qx) and Y (component cyi of row qy);
+// spectra X (component cxi of row rx) and Y (component cyi of row ry);
 // X[m] = (Z[m] + conj Z[L-m]) / 2, Y[m] = (Z[m] - conj Z[L-m]) / (2i), with
 // the real Nyquist values packed into the imaginary slots of bin 0.
-template <typename T, int L, int RMAX, int WT>
-__device__ __forceinline__ void split_store(const cx<T> (&z)[RMAX], T* lre, T* lim, int t, cx<T>* __restrict__ spec,
+template <typename T, int L, int RMAX, int WT, int TSTRIDE>
+__device__ __forceinline__ void split_store(const cx<T> (&z)[RMAX], T* lre, T* lim, int t, cx<T>* __restrict__ base,
                                             int rx, int cxi, int ry, int cyi) {
   constexpr int TPF = L / RMAX;
   __syncthreads();
@@ -242,18 +266,39 @@ __device__ __forceinline__ void split_store(const cx<T> (&z)[RMAX], T* lre, T* l
       X.im = lre[ih];   // Re Z[L/2]: Nyquist bin of x
       Y.im = lim[ih];   // Im Z[L/2]: Nyquist bin of y
     }
-    spec[sidx<L, WT>(mm, rx) + cxi] = X;
-    spec[sidx<L, WT>(mm, ry) + cyi] = Y;
+    base[pidx<WT, TSTRIDE>(mm, rx, cxi)] = X;
+    base[pidx<WT, TSTRIDE>(mm, ry, cyi)] = Y;
   }
 }
 
 // Hermitian extension of a packed row spectrum at bin m in [0, L).
-template <typename T, int L, int WT>
-__device__ __forceinline__ cx<T> load_bin(const cx<T>* __restrict__ spec, int m, int row, int c) {
-  if (m == 0) return {spec[sidx<L, WT>(0, row) + c].re, (T)0};
-  if (m == L / 2) return {spec[sidx<L, WT>(0, row) + c].im, (T)0};
-  if (m < L / 2) return spec[sidx<L, WT>(m, row) + c];
-  return cconj(spec[sidx<L, WT>(L - m, row) + c]);
+template <typename T, int L, int WT, int TSTRIDE>
+__device__ __forceinline__ cx<T> load_bin(const cx<T>* __restrict__ base, int m, int r, int c) {
+  if (m == 0) return {base[pidx<WT, TSTRIDE>(0, r, c)].re, (T)0};
+  if (m == L / 2) return {base[pidx<WT, TSTRIDE>(0, r, c)].im, (T)0};
+  if (m < L / 2) return base[pidx<WT, TSTRIDE>(m, r, c)];
+  return cconj(base[pidx<WT, TSTRIDE>(L - m, r, c)]);
+}
+
+// Copy a row pair's slice of the half spectrum between HBM and its LDS
+// stage in 16-byte units: tile j holds 2 WT 3 contiguous complex values of
+// rows ra, ra + 1 (ra even), so each lane moves 16 contiguous bytes.
+template <typename T, int L, int WT, int TPF, bool TO_LDS>
+__device__ __forceinline__ void stage_copy(cx<T>* __restrict__ g, cx<T>* __restrict__ st, int t) {
+  constexpr int CPT = 2 * WT * 3;                       // complex values per tile and row pair
+  constexpr int UPT = CPT * (int)sizeof(cx<T>) / 16;    // 16-byte units per tile
+  constexpr int NU = (L / 2 / WT) * UPT;
+  static_assert((CPT * sizeof(cx<T>)) % 16 == 0, "tile slice must be a whole number of 16-byte units");
+  const uint4* __restrict__ gs = reinterpret_cast<const uint4*>(g);
+  uint4* __restrict__ gd = reinterpret_cast<uint4*>(g);
+  uint4* __restrict__ ls = reinterpret_cast<uint4*>(st);
+#pragma unroll 4
+  for (int u = t; u < NU; u += TPF) {
+    const int j = u / UPT, k = u - j * UPT;
+    const unsigned gi = (unsigned)j * (L * WT * 3 * (int)sizeof(cx<T>) / 16) + k;
+    if constexpr (TO_LDS) ls[u] = gs[gi];
+    else gd[gi] = ls[u];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -274,33 +319,70 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
   constexpr int LOAD_GROUP = RMAX >= 4 ? 4 : RMAX;   // unrolled iterations whose loads may be in flight together
   constexpr bool LOADS_SPEC = MODE == ROW_ITER || MODE == ROW_INV || MODE == ROW_EMIT;
   constexpr bool POINTWISE = MODE == ROW_ITER || MODE == ROW_INIT;
+  constexpr bool STAGED = RowStage<T, L, TEAMS, TPF>::value;
+  constexpr int GSTRIDE = L * WT * 3, SSTRIDE = 2 * WT * 3;
   if (a.state && a.state->halted) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int team = threadIdx.x / TPF;
   const int t = threadIdx.x % TPF;
   T* lre = reinterpret_cast<T*>(smem_raw) + team * 2 * LS;
   T* lim = lre + LS;
+  // LDS stage of this team's row pair: 3 L complex values after the FFT buffers
+  cx<T>* stg = reinterpret_cast<cx<T>*>(reinterpret_cast<T*>(smem_raw) + TEAMS * 2 * LS) + team * 3 * L;
   const int p = xcd_remap(blockIdx.x, gridDim.x) * TEAMS + team;
   const int ra = 2 * p, rb = 2 * p + 1;
   cx<T>* __restrict__ spec = a.spec;
+  cx<T>* __restrict__ gbase = spec + (size_t)ra * WT * 3;
   const cx<T>* __restrict__ tw = a.tw;
   const Mat<T> m = make_mat<T>(a.prm);
   constexpr unsigned NPX = (unsigned)L * L;
 
   cx<T> za[RMAX], zb[RMAX], zc[RMAX];
 
-  if constexpr (LOADS_SPEC) {
+  // Stress and mask of the thread's pixel pairs, fetched PF pairs ahead of
+  // the pointwise step; the first PF pairs are issued before the inverse
+  // transforms so they arrive while those run.
+  constexpr int PF = PM_ROW_PREFETCH < RMAX ? PM_ROW_PREFETCH : RMAX;
+  T so[RMAX][2][4];
+  uint8_t mk[RMAX][2];
+  auto fetch = [&](int s) {
 #pragma unroll
-    for (int s = 0; s < RMAX; ++s) {
-      const int mm = t + TPF * s;
-      const cx<T> a0 = load_bin<T, L, WT>(spec, mm, ra, 0), a1 = load_bin<T, L, WT>(spec, mm, ra, 1);
-      const cx<T> a2 = load_bin<T, L, WT>(spec, mm, ra, 2);
-      const cx<T> b0 = load_bin<T, L, WT>(spec, mm, rb, 0), b1 = load_bin<T, L, WT>(spec, mm, rb, 1);
-      const cx<T> b2 = load_bin<T, L, WT>(spec, mm, rb, 2);
-      za[s] = {a0.re - a1.im, a0.im + a1.re};
-      zb[s] = {b0.re - b1.im, b0.im + b1.re};
-      zc[s] = {a2.re - b2.im, a2.im + b2.re};
-      if ((s & (LOAD_GROUP - 1)) == LOAD_GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+    for (int half = 0; half < 2; ++half) {
+      const unsigned ix = (unsigned)(half ? rb : ra) * L + t + TPF * s;
+      mk[s][half] = a.mask[ix];
+      if constexpr (MODE == ROW_ITER) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) so[s][half][c] = a.sig[c * NPX + ix];
+      }
+    }
+  };
+  if constexpr (POINTWISE) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) fetch(s);
+  }
+
+  if constexpr (LOADS_SPEC) {
+    auto build = [&](const cx<T>* base, auto tstride) {
+      constexpr int TS = decltype(tstride)::value;
+#pragma unroll
+      for (int s = 0; s < RMAX; ++s) {
+        const int mm = t + TPF * s;
+        const cx<T> a0 = load_bin<T, L, WT, TS>(base, mm, 0, 0), a1 = load_bin<T, L, WT, TS>(base, mm, 0, 1);
+        const cx<T> a2 = load_bin<T, L, WT, TS>(base, mm, 0, 2);
+        const cx<T> b0 = load_bin<T, L, WT, TS>(base, mm, 1, 0), b1 = load_bin<T, L, WT, TS>(base, mm, 1, 1);
+        const cx<T> b2 = load_bin<T, L, WT, TS>(base, mm, 1, 2);
+        za[s] = {a0.re - a1.im, a0.im + a1.re};
+        zb[s] = {b0.re - b1.im, b0.im + b1.re};
+        zc[s] = {a2.re - b2.im, a2.im + b2.re};
+        if ((s & (LOAD_GROUP - 1)) == LOAD_GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    if constexpr (STAGED) {
+      stage_copy<T, L, WT, TPF, true>(gbase, stg, t);
+      __syncthreads();
+      build(stg, std::integral_constant<int, SSTRIDE>{});
+    } else {
+      build(gbase, std::integral_constant<int, GSTRIDE>{});
     }
     fence(za); fence(zb); fence(zc);
     fft<+1, T, L, RMAX>(za, lre, lim, t, tw);
@@ -368,48 +450,23 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
   }
 
   if constexpr (POINTWISE) {
-    // Pointwise step per pixel.  The stress and mask of the next pixel pair
-    // are fetched while the current one is solved.  Per-thread partial sums
+    // Pointwise step per pixel.  Per-thread partial sums
     // (sigma 11, 22, 33, 12 and |e - eps|^2) are kept in LDS rather than
     // registers, which keeps the kernel free of spills; block and global
     // sums are FP64.
     __shared__ T lacc[5][BS];
     T* __restrict__ sig = a.sig;
-    const uint8_t* __restrict__ vm = a.mask;
     const T E0 = (T)a.E[0], E1 = (T)a.E[1], E2 = (T)a.E[2];
-    T so_n[2][4];
-    uint8_t mk_n[2];
-    auto fetch = [&](int s) {
-      const int x1 = t + TPF * s;
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
-        mk_n[half] = vm[ix];
-        if constexpr (MODE == ROW_ITER) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) so_n[half][c] = sig[c * NPX + ix];
-        }
-      }
-    };
 #pragma unroll
     for (int i = 0; i < 5; ++i) lacc[i][threadIdx.x] = (T)0;
-    fetch(0);
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
       const int x1 = t + TPF * s;
-      T so_c[2][4];
-      uint8_t mk_c[2];
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        mk_c[half] = mk_n[half];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) so_c[half][c] = so_n[half][c];
-      }
-      if (s + 1 < RMAX) fetch(s + 1);
+      if (s + PF < RMAX) fetch(s + PF);
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
-        const bool isv = mk_c[half] != 0;
+        const bool isv = mk[s][half] != 0;
         T e[3], en[4], sg[4], tau[3];
         if constexpr (MODE == ROW_INIT) {
           e[0] = E0; e[1] = E1; e[2] = E2;
@@ -426,7 +483,7 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
         } else {
           if (half == 0) { e[0] = za[s].re; e[1] = za[s].im; e[2] = zc[s].re; }
           else { e[0] = zb[s].re; e[1] = zb[s].im; e[2] = zc[s].im; }
-          alm_point(e, so_c[half], isv, m, en, sg, tau);
+          alm_point(e, so[s][half], isv, m, en, sg, tau);
         }
         sig[ix] = sg[0]; sig[NPX + ix] = sg[1]; sig[2 * NPX + ix] = sg[2]; sig[3 * NPX + ix] = sg[3];
         {
@@ -452,9 +509,17 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
   fft<-1, T, L, RMAX>(zc, lre, lim, t, tw);
 
   // Za -> (11, 22) of row a, Zb -> (11, 22) of row b, Zc -> 12 of rows a, b.
-  split_store<T, L, RMAX, WT>(za, lre, lim, t, spec, ra, 0, ra, 1);
-  split_store<T, L, RMAX, WT>(zb, lre, lim, t, spec, rb, 0, rb, 1);
-  split_store<T, L, RMAX, WT>(zc, lre, lim, t, spec, ra, 2, rb, 2);
+  if constexpr (STAGED) {
+    split_store<T, L, RMAX, WT, SSTRIDE>(za, lre, lim, t, stg, 0, 0, 0, 1);
+    split_store<T, L, RMAX, WT, SSTRIDE>(zb, lre, lim, t, stg, 1, 0, 1, 1);
+    split_store<T, L, RMAX, WT, SSTRIDE>(zc, lre, lim, t, stg, 0, 2, 1, 2);
+    __syncthreads();
+    stage_copy<T, L, WT, TPF, false>(gbase, stg, t);
+  } else {
+    split_store<T, L, RMAX, WT, GSTRIDE>(za, lre, lim, t, gbase, 0, 0, 0, 1);
+    split_store<T, L, RMAX, WT, GSTRIDE>(zb, lre, lim, t, gbase, 1, 0, 1, 1);
+    split_store<T, L, RMAX, WT, GSTRIDE>(zc, lre, lim, t, gbase, 0, 2, 1, 2);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -621,7 +686,9 @@ struct Cfg {
 
 template <typename T, int L>
 static size_t row_lds() {
-  return (size_t)Cfg<T, L>::ROW_TEAMS * 2 * LdsSize<L>::value * sizeof(T);
+  using C = Cfg<T, L>;
+  return (size_t)C::ROW_TEAMS * 2 * LdsSize<L>::value * sizeof(T) +
+         (RowStage<T, L, C::ROW_TEAMS, C::TPF>::value ? (size_t)C::ROW_TEAMS * 3 * L * sizeof(cx<T>) : 0);
 }
 template <typename T, int L>
 static size_t col_lds() {
