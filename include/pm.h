@@ -235,6 +235,99 @@ int pm_debug_forward(pm_solver* solver, const void* d_real);
 int pm_debug_inverse(pm_solver* solver, void* d_real);
 int pm_debug_green(pm_solver* solver, const double E[3]);
 
+
+/* ------------------------------------------------------------------------
+ * Batch / serving engine.
+ *
+ * Many independent realizations, each with its own mask, moduli, grid size,
+ * precision and load ramp E_1..E_n, solved together on one stream: every
+ * launch covers all running realizations ("slots") of one (precision, L)
+ * group, and each slot advances along its own ramp on the device, the state
+ * of one load step warm-starting the next exactly as successive calls of
+ * pm_solver_step do (the solved problem is the one of eqs. 1-3 with the
+ * pointwise law of Sec. 2; the load ramp is the stepwise strain history of
+ * Sec. 3).  A slot's step records and fields are bitwise identical to those
+ * of a pm_solver with the same parameters driven through the same ramp: the
+ * kernels and the fixed-order reductions are the same, per slot.
+ *
+ * Memory: the caller passes one device pool.  The engine keeps its fixed
+ * part (pm_batch_overhead_bytes) at the start of the pool and carves each
+ * slot's workspace (pm_batch_slot_bytes) out of the rest, first fit; it
+ * never allocates device memory.  Admission fails with PM_EBUSY when the
+ * pool has no free range of that size or all max_slots slots are in use.
+ *
+ * Threading: a pm_batch is bound to its stream and is not thread-safe.
+ * Masks passed to pm_batch_admit must stay alive until pm_batch_release.
+ * ---------------------------------------------------------------------- */
+typedef struct pm_batch pm_batch;
+
+/* One load step's result, written by the device when the step ends. */
+typedef struct pm_step_record {
+  double sigma_mean[4];      /* <sigma> 11, 22, 33, 12 (FP64) */
+  double eps_mean[4];        /* <eps> of the recovered strain */
+  double res_eq, res_mac, res_cmp;
+  double plastic_fraction;   /* pixels on the capped branch in the last iteration / L^2 */
+  int32_t iters;
+  int32_t status;            /* 1 converged, 2 stopped at max_iter, 3 non-finite value */
+} pm_step_record;
+
+#define PM_STEP_CONVERGED 1
+#define PM_STEP_NOCONV 2
+#define PM_STEP_NAN 3
+
+/* State of a slot as of the end of the last pm_batch_tick. */
+typedef struct pm_slot_info {
+  int32_t L, precision, nsteps;
+  int32_t steps_done;        /* records 0 .. steps_done-1 are final */
+  int32_t finished;          /* 1: all steps done, or stopped at a non-finite value */
+  int32_t last_status;       /* status of the last finished step (0 if none) */
+} pm_slot_info;
+
+/* Fixed part of the pool for max_slots slots (slot states, the device slot
+ * table and the twiddle / momentum tables of every grid size). */
+size_t pm_batch_overhead_bytes(int32_t max_slots);
+
+/* Pool bytes one slot with these parameters and nsteps load steps takes
+ * (state, half spectrum, partial sums, ramp and step records); 0 if params
+ * are invalid. */
+size_t pm_batch_slot_bytes(const pm_params* params, int32_t nsteps);
+
+/* d_pool: device memory of pool_bytes bytes, 256-byte aligned, owned by the
+ * caller and kept alive until pm_batch_destroy.  1 <= max_slots <= 65536. */
+int pm_batch_create(pm_batch** out, void* d_pool, size_t pool_bytes, int32_t max_slots, void* stream);
+
+/* Admit a realization.  d_void_mask: device, L x L row-major [x2][x1],
+ * 1 = void.  E_path: host, nsteps x 3 (E11, E22, E12 per step, each of
+ * nonzero finite norm), copied.  On success *slot receives the slot id.
+ * The first step starts from the uniform state of that step's E (as the
+ * first pm_solver_step).  The work is queued on the batch's stream; it
+ * runs with the next ticks.  Returns PM_EBUSY (nothing changed) when the
+ * pool or the slot table is full. */
+int pm_batch_admit(pm_batch* batch, const pm_params* params, const uint8_t* d_void_mask, int32_t nsteps,
+                   const double* E_path, int32_t* slot);
+
+/* Run iters augmented-Lagrangian iterations on every running slot, then end
+ * the load steps that finished (output pass for <eps>, record, start of the
+ * next step), then read back every slot's state (blocking).  A slot whose
+ * step ends during a tick waits for the end of that tick.  *running (may be
+ * NULL) receives the number of slots not finished. */
+int pm_batch_tick(pm_batch* batch, int32_t iters, int32_t* running);
+
+int pm_batch_poll(pm_batch* batch, int32_t slot, pm_slot_info* info);
+
+/* Copy step records first .. first+count-1 (all < steps_done) to host. */
+int pm_batch_records(pm_batch* batch, int32_t slot, int32_t first, int32_t count, pm_step_record* out);
+
+/* Write the slot's current fields (sigma, eps, plastic mask; device
+ * pointers of pm_step_out, NULL = skip) and means, as pm_solver_step does
+ * after a step.  Meaningful once steps_done > 0; blocking. */
+int pm_batch_fetch(pm_batch* batch, int32_t slot, pm_step_out* out);
+
+/* Free the slot's pool range and id.  A slot that is still running is
+ * stopped.  Blocking (waits for queued work). */
+int pm_batch_release(pm_batch* batch, int32_t slot);
+int pm_batch_destroy(pm_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,24 @@ class PmKernelTiming(ctypes.Structure):
     ]
 
 
+class PmStepRecord(ctypes.Structure):
+    _fields_ = [
+        ("sigma_mean", ctypes.c_double * 4), ("eps_mean", ctypes.c_double * 4),
+        ("res_eq", ctypes.c_double), ("res_mac", ctypes.c_double), ("res_cmp", ctypes.c_double),
+        ("plastic_fraction", ctypes.c_double),
+        ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+    ]
+
+
+class PmSlotInfo(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32), ("precision", ctypes.c_int32), ("nsteps", ctypes.c_int32),
+        ("steps_done", ctypes.c_int32), ("finished", ctypes.c_int32), ("last_status", ctypes.c_int32),
+    ]
+
+
+PM_STEP_CONVERGED, PM_STEP_NOCONV, PM_STEP_NAN = 1, 2, 3
+
 # (name, restype, argtypes) of every entry point in include/pm.h
 SIGNATURES = [
     ("pm_status_string", ctypes.c_char_p, [ctypes.c_int]),
@@ -65,6 +83,20 @@ SIGNATURES = [
     ("pm_debug_forward", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("pm_debug_inverse", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("pm_debug_green", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    ("pm_batch_overhead_bytes", ctypes.c_size_t, [ctypes.c_int32]),
+    ("pm_batch_slot_bytes", ctypes.c_size_t, [ctypes.POINTER(PmParams), ctypes.c_int32]),
+    ("pm_batch_create", ctypes.c_int,
+     [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p]),
+    ("pm_batch_admit", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.POINTER(PmParams), ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+      ctypes.POINTER(ctypes.c_int32)]),
+    ("pm_batch_tick", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    ("pm_batch_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(PmSlotInfo)]),
+    ("pm_batch_records", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(PmStepRecord)]),
+    ("pm_batch_fetch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(PmStepOut)]),
+    ("pm_batch_release", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("pm_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
 ]
 
 _lib = None

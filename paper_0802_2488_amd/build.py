@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpm.so")
-SOURCES = ["pm_row_f32.hip", "pm_row_f64.hip", "pm_col_f32.hip", "pm_col_f64.hip", "pm_misc.hip", "pm_api.hip"]
+SOURCES = ["pm_row_f32.hip", "pm_row_f64.hip", "pm_col_f32.hip", "pm_col_f64.hip", "pm_misc.hip", "pm_api.hip",
+           "pm_batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -11,14 +11,22 @@
 #include <vector>
 
 #include "pm.h"
+#include "pm_host.hpp"
 #include "pm_internal.h"
 
 using pm::DevParams;
 using pm::DevState;
+using pmh::fail;
+using pmh::Layout;
+
+static_assert(sizeof(pm::Slot<float>) == sizeof(pm::Slot<double>), "slot layout must not depend on T");
+static_assert(sizeof(pm::StepRecord) == sizeof(pm_step_record), "device and public step records differ");
+
+namespace pmh {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -30,23 +38,8 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define PM_HIP(call)                                                                      \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess) return fail(PM_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
+const char* last_error() { return g_err.c_str(); }
 
-bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-struct Layout {
-  size_t sig, spec, xbuf, tw, ktab, part, part2, state, total;
-  int tile;
-  int nrow, ndiv;
-};
-
-// Resolve defaults and validate; fills *q.
 int check_params(const pm_params* p, pm_params* q) {
   if (!p) return fail(PM_EINVAL, "params is NULL");
   *q = *p;
@@ -69,13 +62,25 @@ int check_params(const pm_params* p, pm_params* q) {
   return PM_OK;
 }
 
-Layout make_layout(const pm_params& q) {
+DevParams dev_params(const pm_params& q) {
+  DevParams d{};
+  d.mu = q.mu; d.lam = q.lambda; d.Y = q.Y; d.mu0 = q.mu0; d.lam0 = q.lambda0;
+  d.K = q.lambda + 2.0 * q.mu / 3.0;
+  d.K0 = q.lambda0 + 2.0 * q.mu0 / 3.0;
+  d.sy = std::sqrt(2.0 / 3.0) * q.Y;
+  d.npx = (double)q.L * (double)q.L;
+  d.eta_eq = q.eta_eq; d.eta_mac = q.eta_mac; d.eta_cmp = q.eta_cmp;
+  d.max_iter = q.max_iter;
+  d.L = q.L;
+  return d;
+}
+
+Layout make_layout(const pm_params& q, bool tables, bool state) {
   Layout lo{};
   const size_t L = (size_t)q.L;
   const size_t fs = q.precision == PM_FP64 ? 8 : 4;
-  lo.tile = pm_spectrum_tile(q.L, q.precision);
-  lo.nrow = q.precision == PM_FP64 ? pm::row_grid<double>(q.L) : pm::row_grid<float>(q.L);
-  lo.ndiv = std::max(pm::div_grid(q.L), 4 * lo.nrow);
+  lo.nrow = q.precision == PM_FP64 ? pm::row_blocks<double>(q.L) : pm::row_blocks<float>(q.L);
+  lo.ndiv = std::max(pm::div_blocks(q.L), 4 * lo.nrow);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -85,33 +90,35 @@ Layout make_layout(const pm_params& q) {
   lo.sig = take(4 * L * L * fs);
   lo.spec = take(L * (L / 2) * 3 * 2 * fs);
   lo.xbuf = take(3 * L * 2 * fs);
-  lo.tw = take(L * 2 * fs);
-  lo.ktab = take(L * 2 * fs);
+  lo.tw = tables ? take(L * 2 * fs) : 0;
+  lo.ktab = tables ? take(L * 2 * fs) : 0;
   lo.part = take((size_t)lo.nrow * pm::NPART * sizeof(double));
   lo.part2 = take((size_t)lo.ndiv * sizeof(double));
-  lo.state = take(sizeof(DevState));
+  lo.state = state ? take(sizeof(DevState)) : 0;
+  lo.slot = state ? take(sizeof(pm::Slot<double>)) : 0;
   lo.total = off;
   return lo;
 }
 
-}  // namespace
+uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace pmh
 
 struct pm_solver {
   pm_params p;
-  DevParams prm;
   Layout lo;
   hipStream_t stream;
   int device;
-  const uint8_t* mask;
   char* ws;
   void* sig;       // state: stress of the last iterate (4 planes)
   void* spec;
-  void* tw;
-  void* ktab;
-  double* part;
-  double* part2;
-  void* xbuf;
   DevState* st;
+  void* slot;      // device table of one pm::Slot<T>
   DevState* hst;   // pinned host copies (two slots)
   hipEvent_t ev[2];
   bool started;
@@ -125,70 +132,39 @@ struct pm_solver {
 namespace {
 
 template <typename T>
-int upload_tables(pm_solver* s) {
+const pm::Slot<T>* dslot(const pm_solver* s) {
+  return (const pm::Slot<T>*)s->slot;
+}
+
+// Tables and the one-entry slot table, uploaded once at create.
+template <typename T>
+int upload_tables(pm_solver* s, const uint8_t* mask) {
   const int L = s->p.L;
-  std::vector<pm::cx<T>> tw(L), kt(L);
-  for (int i = 0; i < L; ++i) {
-    // exp(-2 pi i i / L), and k(m) = 2 sin(q/2) exp(i q/2) = sin q + i 2 sin^2(q/2)
-    const double a = 2.0 * M_PI * (double)i / (double)L;
-    tw[i].re = (T)std::cos(a);
-    tw[i].im = (T)(-std::sin(a));
-    const double h = std::sin(0.5 * a);
-    kt[i].re = (T)std::sin(a);
-    kt[i].im = (T)(2.0 * h * h);
-  }
-  PM_HIP(hipMemcpyAsync(s->tw, tw.data(), L * sizeof(pm::cx<T>), hipMemcpyHostToDevice, s->stream));
-  PM_HIP(hipMemcpyAsync(s->ktab, kt.data(), L * sizeof(pm::cx<T>), hipMemcpyHostToDevice, s->stream));
+  std::vector<pm::cx<T>> tw, kt;
+  pmh::make_tables<T>(L, tw, kt);
+  char* tw_d = s->ws + s->lo.tw;
+  char* kt_d = s->ws + s->lo.ktab;
+  const pm::Slot<T> S = pmh::make_slot<T>(s->p, s->ws, s->lo, mask, tw_d, kt_d, s->st);
+  PM_HIP(hipMemcpyAsync(tw_d, tw.data(), L * sizeof(pm::cx<T>), hipMemcpyHostToDevice, s->stream));
+  PM_HIP(hipMemcpyAsync(kt_d, kt.data(), L * sizeof(pm::cx<T>), hipMemcpyHostToDevice, s->stream));
+  PM_HIP(hipMemcpyAsync(s->slot, &S, sizeof S, hipMemcpyHostToDevice, s->stream));
   PM_HIP(hipStreamSynchronize(s->stream));
   return PM_OK;
 }
 
 template <typename T>
-pm::RowArgs<T> row_args(pm_solver* s, int mode, const double* E, bool with_state) {
-  pm::RowArgs<T> a{};
-  a.spec = (pm::cx<T>*)s->spec;
-  a.tw = (const pm::cx<T>*)s->tw;
-  a.sig = (T*)s->sig;
-  a.mask = s->mask;
-  a.partials = s->part;
-  a.state = with_state ? s->st : nullptr;
-  a.mode = mode;
-  for (int i = 0; i < 3; ++i) a.E[i] = E ? E[i] : 0.0;
-  a.prm = s->prm;
-  return a;
-}
-
-template <typename T>
-pm::ColArgs<T> col_args(pm_solver* s, int mode, double scale, const double* E, bool with_state) {
-  pm::ColArgs<T> a{};
-  a.spec = (pm::cx<T>*)s->spec;
-  a.tw = (const pm::cx<T>*)s->tw;
-  a.ktab = (const pm::cx<T>*)s->ktab;
-  a.state = with_state ? s->st : nullptr;
-  a.xbuf = (pm::cx<T>*)s->xbuf;
-  a.mode = mode;
-  const int v = s->p.green_variant;
-  a.flip1 = (v == 1 || v == 2) ? 1 : 0;
-  a.flip2 = (v == 1 || v == 3) ? 1 : 0;
-  a.lam0 = s->p.lambda0;
-  a.mu0 = s->p.mu0;
-  a.scale = scale;
-  for (int i = 0; i < 3; ++i) a.E[i] = E ? E[i] : 0.0;
-  return a;
-}
-
-template <typename T>
 int iterate_once(pm_solver* s, int slot_in_chunk) {
   const int L = s->p.L;
-  const double sc = 1.0 / ((double)L * (double)L);
+  const pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_RUNNING, 1.0 / ((double)L * (double)L), nullptr);
+  const pm::Slot<T>* S = dslot<T>(s);
   hipEvent_t* ev = s->timing ? &s->tev[4 * slot_in_chunk] : nullptr;
   if (ev) PM_HIP(hipEventRecord(ev[0], s->stream));
-  PM_HIP(pm::launch_col<T>(L, col_args<T>(s, pm::COL_ALL, sc, nullptr, true), s->stream));
+  PM_HIP(pm::launch_col<T>(L, pm::COL_ALL, S, 1, x, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[1], s->stream));
-  PM_HIP(pm::launch_row<T>(L, row_args<T>(s, pm::ROW_ITER, nullptr, true), s->stream));
+  PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, S, 1, x, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[2], s->stream));
-  PM_HIP(pm::launch_reduce(s->part, s->lo.nrow, s->st, s->prm, s->stream));
-  PM_HIP(pm::launch_div<T>((const T*)s->sig, s->part2, s->st, s->prm, L, 0, s->stream));
+  PM_HIP(pm::launch_reduce<T>(S, 1, s->lo.nrow, s->stream));
+  PM_HIP(pm::launch_div<T>(S, 1, L, 0, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[3], s->stream));
   return PM_OK;
 }
@@ -214,30 +190,36 @@ int collect_timing(pm_solver* s, int executed) {
 // FP64 mean strain into the device state.
 template <typename T>
 int emit(pm_solver* s, pm_step_out* out) {
-  auto ra = row_args<T>(s, pm::ROW_EMIT, nullptr, false);
+  pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, nullptr);
   if (out) {
-    ra.sig_out = (T*)out->sigma;
-    ra.eps_out = (T*)out->eps;
-    ra.plastic_out = out->plastic;
+    x.sig_out = (T*)out->sigma;
+    x.eps_out = (T*)out->eps;
+    x.plastic_out = out->plastic;
   }
-  ra.partials = s->part2;
-  PM_HIP(pm::launch_row<T>(s->p.L, ra, s->stream));
-  PM_HIP(pm::launch_reduce_emit(s->part2, s->lo.nrow, s->st, (double)s->p.L * s->p.L, s->stream));
+  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_EMIT, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_reduce_emit<T>(dslot<T>(s), 1, s->lo.nrow, pm::GATE_ALL, s->stream));
+  return PM_OK;
+}
+
+template <typename T>
+int init_state(pm_solver* s, const double* E) {
+  const pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, E);
+  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_INIT, dslot<T>(s), 1, x, s->stream));
   return PM_OK;
 }
 
 template <typename T>
 int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
-  const int L = s->p.L;
   const double nE = std::sqrt(E[0] * E[0] + E[1] * E[1] + 2.0 * E[2] * E[2]);
   if (!std::isfinite(nE)) return fail(PM_EINVAL, "E is not finite");
   if (nE == 0.0) {
     // Zero load: the zero field is the solution; reset the state to it.
     const double z[3] = {0.0, 0.0, 0.0};
-    PM_HIP(pm::launch_row<T>(L, row_args<T>(s, pm::ROW_INIT, z, false), s->stream));
+    int rc = init_state<T>(s, z);
+    if (rc != PM_OK) return rc;
     s->started = true;
     if (out && (out->sigma || out->eps || out->plastic)) {
-      int rc = emit<T>(s, out);
+      rc = emit<T>(s, out);
       if (rc != PM_OK) return rc;
     }
     PM_HIP(hipStreamSynchronize(s->stream));
@@ -251,10 +233,11 @@ int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
     return PM_OK;
   }
   if (!s->started) {
-    PM_HIP(pm::launch_row<T>(L, row_args<T>(s, pm::ROW_INIT, E, false), s->stream));
+    int rc = init_state<T>(s, E);
+    if (rc != PM_OK) return rc;
     s->started = true;
   }
-  PM_HIP(pm::launch_begin(s->st, E, 1e-12 * s->p.mu * nE, s->stream));
+  PM_HIP(pm::launch_begin(s->st, E, s->p.mu, 0, 1, s->stream));
   const int max_iter = s->p.max_iter;
   int issued = 0, slot = 0, pend = -1, fin = -1;
   while (fin < 0 && s->timing) {
@@ -273,6 +256,7 @@ int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
     if (s->hst[0].halted || issued >= max_iter) fin = 0;
   }
   while (fin < 0) {
+    // pipelined: the next chunk is queued before the previous chunk's state is read
     if (issued < max_iter) {
       const int n = std::min(s->chunk, max_iter - issued);
       for (int i = 0; i < n; ++i) {
@@ -295,10 +279,6 @@ int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
     }
   }
   if (!s->hst[fin].halted) return fail(PM_EDEVICE, "device did not halt after max_iter iterations");
-  if (s->hst[fin].status != pm::ST_CONVERGED) {
-    // report the equilibrium indicator of the final iterate
-    PM_HIP(pm::launch_div<T>((const T*)s->sig, s->part2, s->st, s->prm, L, 1, s->stream));
-  }
   // outputs and <eps> (always), then the final state
   {
     int rc = emit<T>(s, out);
@@ -327,33 +307,32 @@ int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
   return rc;
 }
 
-}  // namespace
-
-namespace {
 template <typename T>
 int debug_forward(pm_solver* s, const void* d_real) {
-  auto ra = row_args<T>(s, pm::ROW_FWD, nullptr, false);
-  ra.real_in = (const T*)d_real;
-  PM_HIP(pm::launch_row<T>(s->p.L, ra, s->stream));
-  PM_HIP(pm::launch_col<T>(s->p.L, col_args<T>(s, pm::COL_FWD, 1.0, nullptr, false), s->stream));
+  pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, nullptr);
+  x.real_in = (const T*)d_real;
+  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_FWD, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_col<T>(s->p.L, pm::COL_FWD, dslot<T>(s), 1, x, s->stream));
   PM_HIP(hipStreamSynchronize(s->stream));
   return PM_OK;
 }
 template <typename T>
 int debug_inverse(pm_solver* s, void* d_real) {
-  PM_HIP(pm::launch_col<T>(s->p.L, col_args<T>(s, pm::COL_INV, 1.0, nullptr, false), s->stream));
-  auto ra = row_args<T>(s, pm::ROW_INV, nullptr, false);
-  ra.real_out = (T*)d_real;
-  PM_HIP(pm::launch_row<T>(s->p.L, ra, s->stream));
+  pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, nullptr);
+  x.real_out = (T*)d_real;
+  PM_HIP(pm::launch_col<T>(s->p.L, pm::COL_INV, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_INV, dslot<T>(s), 1, x, s->stream));
   PM_HIP(hipStreamSynchronize(s->stream));
   return PM_OK;
 }
 template <typename T>
 int debug_green(pm_solver* s, const double* E) {
-  PM_HIP(pm::launch_col<T>(s->p.L, col_args<T>(s, pm::COL_GREEN, 1.0, E, false), s->stream));
+  const pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, E);
+  PM_HIP(pm::launch_col<T>(s->p.L, pm::COL_GREEN, dslot<T>(s), 1, x, s->stream));
   PM_HIP(hipStreamSynchronize(s->stream));
   return PM_OK;
 }
+
 }  // namespace
 
 extern "C" {
@@ -370,10 +349,11 @@ const char* pm_status_string(int status) {
   }
 }
 
-const char* pm_last_error(void) { return g_err.c_str(); }
+const char* pm_last_error(void) { return pmh::last_error(); }
 
 int32_t pm_spectrum_tile(int32_t L, int32_t precision) {
-  if (!is_pow2(L) || L < 4 || L > PM_MAX_L) return fail(PM_EINVAL, "L = %d must be a power of two in [4, %d]", L, PM_MAX_L);
+  if (!pmh::is_pow2(L) || L < 4 || L > PM_MAX_L)
+    return fail(PM_EINVAL, "L = %d must be a power of two in [4, %d]", L, PM_MAX_L);
   if (precision == PM_FP32) return pm::tile_width<float>(L);
   if (precision == PM_FP64) return pm::tile_width<double>(L);
   return fail(PM_EINVAL, "precision must be PM_FP32 or PM_FP64");
@@ -381,8 +361,8 @@ int32_t pm_spectrum_tile(int32_t L, int32_t precision) {
 
 size_t pm_workspace_bytes(const pm_params* params) {
   pm_params q;
-  if (check_params(params, &q) != PM_OK) return 0;
-  return make_layout(q).total;
+  if (pmh::check_params(params, &q) != PM_OK) return 0;
+  return pmh::make_layout(q, true, true).total;
 }
 
 int pm_solver_create(pm_solver** out, const pm_params* params, const uint8_t* d_void_mask, void* d_workspace,
@@ -390,11 +370,11 @@ int pm_solver_create(pm_solver** out, const pm_params* params, const uint8_t* d_
   if (!out) return fail(PM_EINVAL, "out is NULL");
   *out = nullptr;
   pm_params q;
-  int rc = check_params(params, &q);
+  int rc = pmh::check_params(params, &q);
   if (rc != PM_OK) return rc;
   if (!d_void_mask || !d_workspace) return fail(PM_EINVAL, "mask and workspace must be device pointers");
   if (((uintptr_t)d_workspace) % 256 != 0) return fail(PM_EINVAL, "workspace must be 256-byte aligned");
-  Layout lo = make_layout(q);
+  const Layout lo = pmh::make_layout(q, true, true);
   if (workspace_bytes < lo.total)
     return fail(PM_EINVAL, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, lo.total);
   pm_solver* s = new (std::nothrow) pm_solver();
@@ -402,29 +382,15 @@ int pm_solver_create(pm_solver** out, const pm_params* params, const uint8_t* d_
   s->p = q;
   s->lo = lo;
   s->stream = (hipStream_t)stream;
-  s->mask = d_void_mask;
   s->ws = (char*)d_workspace;
   s->sig = s->ws + lo.sig;
   s->spec = s->ws + lo.spec;
-  s->tw = s->ws + lo.tw;
-  s->ktab = s->ws + lo.ktab;
-  s->part = (double*)(s->ws + lo.part);
-  s->part2 = (double*)(s->ws + lo.part2);
-  s->xbuf = s->ws + lo.xbuf;
   s->st = (DevState*)(s->ws + lo.state);
+  s->slot = s->ws + lo.slot;
   s->started = false;
   const long L2 = (long)q.L * q.L;
   s->chunk = q.check_every > 0 ? q.check_every
                                : (int)std::max(8L, std::min(128L, (long)(1L << 27) / L2));
-  DevParams& d = s->prm;
-  d.mu = q.mu; d.lam = q.lambda; d.Y = q.Y; d.mu0 = q.mu0; d.lam0 = q.lambda0;
-  d.K = q.lambda + 2.0 * q.mu / 3.0;
-  d.K0 = q.lambda0 + 2.0 * q.mu0 / 3.0;
-  d.sy = std::sqrt(2.0 / 3.0) * q.Y;
-  d.npx = (double)L2;
-  d.eta_eq = q.eta_eq; d.eta_mac = q.eta_mac; d.eta_cmp = q.eta_cmp;
-  d.max_iter = q.max_iter;
-  d.L = q.L;
   auto cleanup = [&](int code) {
     if (s->hst) (void)hipHostFree(s->hst);
     for (int i = 0; i < 2; ++i)
@@ -441,7 +407,7 @@ int pm_solver_create(pm_solver** out, const pm_params* params, const uint8_t* d_
       return cleanup(fail(PM_EDEVICE, "hipEventCreate failed"));
   if (hipMemsetAsync(s->st, 0, sizeof(DevState), s->stream) != hipSuccess)
     return cleanup(fail(PM_EDEVICE, "hipMemsetAsync failed"));
-  rc = q.precision == PM_FP64 ? upload_tables<double>(s) : upload_tables<float>(s);
+  rc = q.precision == PM_FP64 ? upload_tables<double>(s, d_void_mask) : upload_tables<float>(s, d_void_mask);
   if (rc != PM_OK) return cleanup(rc);
   *out = s;
   return PM_OK;
@@ -502,13 +468,6 @@ int pm_debug_green(pm_solver* s, const double E[3]) {
   return s->p.precision == PM_FP64 ? debug_green<double>(s, E) : debug_green<float>(s, E);
 }
 
-static uint64_t host_splitmix64(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 int pm_bernoulli_mask(uint8_t* dst, int32_t L, double f, uint64_t seed, int32_t on_device, void* stream) {
   if (!dst) return fail(PM_EINVAL, "dst is NULL");
   if (L < 1 || L > 65536) return fail(PM_EINVAL, "L = %d out of range", L);
@@ -520,7 +479,7 @@ int pm_bernoulli_mask(uint8_t* dst, int32_t L, double f, uint64_t seed, int32_t 
     return PM_OK;
   }
   for (long p = 0; p < npx; ++p) {
-    const uint64_t z = host_splitmix64(seed ^ host_splitmix64((uint64_t)p));
+    const uint64_t z = pmh::splitmix64(seed ^ pmh::splitmix64((uint64_t)p));
     dst[p] = ((double)(z >> 11) * 0x1.0p-53) < f ? 1 : 0;
   }
   return PM_OK;

@@ -1,4 +1,9 @@
 // Internal device/host interface between the C-ABI layer and the kernels.
+//
+// Every kernel works on a table of "slots": one slot is one realization
+// (mask, state, half spectrum, partial sums) solved on the device.  A launch
+// covers all slots of one grid size L; block b works on slot b / bps
+// (bps = blocks per slot).  A single solver is a table of one slot.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -11,17 +16,32 @@ enum RowMode { ROW_ITER = 0, ROW_INIT = 1, ROW_FWD = 2, ROW_INV = 3, ROW_EMIT = 
 enum ColMode { COL_FWD = 1, COL_GREEN = 2, COL_INV = 4, COL_ALL = 7 };
 enum Status { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NOCONV = 2, ST_NAN = 3 };
 
-constexpr int NPART = 16;   // doubles per block in the row-pass partials
+constexpr int NPART = 8;    // doubles per block in the row-pass partials
+constexpr int NSUM = 6;     // sigma 11, 22, 33, 12; |e - eps|^2; plastic pixels
 
-// Convergence state of one solve, resident on the device.
+// Result of one load step, written by the device.  Same layout as the
+// public pm_step_record.
+struct StepRecord {
+  double sm[4];                // <sigma> (11, 22, 33, 12)
+  double em[4];                // <eps>
+  double res_eq, res_mac, res_cmp;
+  double plastic;              // fraction of pixels on the capped branch
+  int32_t iters, status;       // status: ST_CONVERGED / ST_NOCONV / ST_NAN
+};
+
+// Convergence state of one slot, resident on the device.
 struct DevState {
   double E[4];                 // E11, E22, E12 of the current load step
   double sm[4], sm_prev[4];    // <sigma> (11, 22, 33, 12), current and previous iteration
-  double em[4];                // <eps>
+  double em[4];                // <eps> (output pass)
   double res_eq, res_mac, res_cmp;
   double normE, floor_s;       // |E| and the floor of the stress normalisation
-  int32_t iter, halted, status, need_eq;
-  int32_t pad[4];
+  double plastic;              // plastic fraction of the last iteration
+  int32_t iter, halted, status;
+  int32_t need_eq;             // 1: test equilibrium; 2: evaluate it for the record at max_iter
+  int32_t step, nsteps;        // load-ramp position when the device advances steps itself
+  int32_t finished;            // all steps of the ramp done
+  int32_t pending;             // a step ended; its record waits for the output pass
 };
 
 struct DevParams {
@@ -32,52 +52,66 @@ struct DevParams {
   int32_t max_iter, L;
 };
 
+// One realization as seen by the kernels.
 template <typename T>
-struct RowArgs {
-  cx<T>* spec;
-  const cx<T>* tw;
-  T* sig;          // state: stress of the last iterate (= multiplier), 4 planes
-  const uint8_t* mask;
-  double* partials;
-  DevState* state;
-  const T* real_in;
-  T* real_out;
-  T* sig_out;      // ROW_EMIT outputs (may be null)
+struct Slot {
+  cx<T>* spec;           // half spectrum (tiled, packed)
+  T* sig;                // state: stress of the last iterate (= multiplier), 4 planes
+  const uint8_t* mask;   // 1 = void
+  double* part;          // per-block partial sums of the row pass (NPART each)
+  double* part2;         // residual and output-pass partial sums
+  cx<T>* xbuf;           // 3 L values: transform of the packed column 0
+  DevState* st;
+  const cx<T>* tw;       // twiddles exp(-2 pi i m / L)
+  const cx<T>* ktab;     // momenta k(m) = 2 sin(q/2) exp(i q/2)
+  const double* E_path;  // device ramp (nsteps x 3) when steps advance on the device, else null
+  StepRecord* rec;       // per-step records (nsteps), or null
+  DevParams prm;
+  int32_t flip1, flip2;  // Green tensor evaluated at -q1 / -q2
+  int32_t pad[2];
+};
+
+// Which slots of a table a launch works on.
+enum Gate { GATE_ALL = 0, GATE_RUNNING = 1, GATE_PENDING = 2 };
+
+// Extra arguments of the check and output modes.
+template <typename T>
+struct Extra {
+  const T* real_in;      // ROW_FWD: 3 planes
+  T* real_out;           // ROW_INV: 3 planes
+  T* sig_out;            // ROW_EMIT outputs (may be null)
   T* eps_out;
   uint8_t* plastic_out;
-  int mode;
-  double E[3];
-  DevParams prm;
+  double E[3];           // ROW_INIT / COL_GREEN when use_state = 0: mean strain
+  double scale;          // Green-tensor output scale (1/L^2 in the iteration)
+  int32_t use_state;     // 1: E from the slot state
+  int32_t gate;          // Gate: skip halted slots, or slots without a pending record
 };
 
 template <typename T>
-struct ColArgs {
-  cx<T>* spec;
-  const cx<T>* tw;
-  const cx<T>* ktab;
-  DevState* state;
-  cx<T>* xbuf;   // 3 L values: transform of the packed column 0
-  int mode;
-  int flip1, flip2;
-  double lam0, mu0, scale;
-  double E[3];
-};
+__device__ __forceinline__ bool gated_out(const Extra<T>& x, const DevState* st) {
+  return (x.gate == GATE_RUNNING && st->halted) || (x.gate == GATE_PENDING && !st->pending);
+}
 
 template <typename T>
-hipError_t launch_row(int L, const RowArgs<T>& a, hipStream_t st);
+hipError_t launch_row(int L, int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st);
 template <typename T>
-hipError_t launch_col(int L, const ColArgs<T>& a, hipStream_t st);
+hipError_t launch_col(int L, int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st);
 template <typename T>
-int row_grid(int L);
+int row_blocks(int L);      // blocks per slot of the row pass
 template <typename T>
 int tile_width(int L);
-int div_grid(int L);
-hipError_t launch_reduce(const double* partials, int nblk, DevState* st, const DevParams& prm, hipStream_t s);
+int div_blocks(int L);      // blocks per slot of the residual pass
 template <typename T>
-hipError_t launch_div(const T* sig, double* partials, DevState* st, const DevParams& prm, int L, int force,
-                      hipStream_t s);
-hipError_t launch_begin(DevState* st, const double* E, double floor_s, hipStream_t s);
-hipError_t launch_reduce_emit(const double* partials, int nblk, DevState* st, double npx, hipStream_t s);
+hipError_t launch_reduce(const Slot<T>* slots, int nslots, int nblk, hipStream_t s);
+template <typename T>
+hipError_t launch_div(const Slot<T>* slots, int nslots, int L, int force, hipStream_t s);
+template <typename T>
+hipError_t launch_reduce_emit(const Slot<T>* slots, int nslots, int nblk, int gate, hipStream_t s);
+template <typename T>
+hipError_t launch_advance(const Slot<T>* slots, int nslots, hipStream_t s);
+hipError_t launch_begin(DevState* st, const double* E, double mu, int32_t step, int32_t nsteps,
+                        hipStream_t s);
 hipError_t launch_mask(uint8_t* out, long npx, double f, uint64_t seed, hipStream_t s);
 
 }  // namespace pm

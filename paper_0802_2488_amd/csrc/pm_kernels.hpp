@@ -105,9 +105,10 @@ __device__ __forceinline__ bool hencky(const T* e, T* s, const Mat<T>& m) {
 // r = dev R: s = c r, c = min(mu / (mu + mu0), sqrt(2/3) Y / |r|) (the elastic
 // and the capped branch in one formula), dev eps = (r - s) / (2 mu0).
 // Voids carry no stress: eps = e (in plane), eps33 = 0.
-// Outputs the new stress (the next multiplier), eps and tau = sigma - C0:eps.
+// Outputs the new stress (the next multiplier), eps and tau = sigma - C0:eps;
+// returns whether the pixel is on the capped (plastic) branch.
 template <typename T>
-__device__ __forceinline__ void alm_point(const T* e, const T* la, bool is_void, const Mat<T>& m, T* en, T* sg,
+__device__ __forceinline__ bool alm_point(const T* e, const T* la, bool is_void, const Mat<T>& m, T* en, T* sg,
                                           T* tau) {
   if (is_void) {
     en[0] = e[0]; en[1] = e[1]; en[2] = (T)0; en[3] = e[2];
@@ -116,7 +117,7 @@ __device__ __forceinline__ void alm_point(const T* e, const T* la, bool is_void,
     tau[0] = -(tr + (T)2 * m.mu0 * e[0]);
     tau[1] = -(tr + (T)2 * m.mu0 * e[1]);
     tau[2] = -((T)2 * m.mu0 * e[2]);
-    return;
+    return false;
   }
   const T tre = m.lam0 * (e[0] + e[1]);
   const T R0 = la[0] + tre + (T)2 * m.mu0 * e[0];
@@ -140,6 +141,7 @@ __device__ __forceinline__ void alm_point(const T* e, const T* la, bool is_void,
   tau[0] = sg[0] - (c0t + (T)2 * m.mu0 * en[0]);
   tau[1] = sg[1] - (c0t + (T)2 * m.mu0 * en[1]);
   tau[2] = sg[3] - (T)2 * m.mu0 * en[3];
+  return cap < m.cel;
 }
 
 // Strain from the stored stress and the polarisation tau = sigma - C0:eps of
@@ -223,7 +225,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 template <typename T, int L, int TEAMS, int TPF>
 struct RowStage {
   static constexpr size_t bytes = (size_t)TEAMS * 2 * LdsSize<L>::value * sizeof(T) +
-                                  (size_t)TEAMS * 3 * L * 2 * sizeof(T) + 5 * (size_t)TEAMS * TPF * sizeof(T) + 16 * 5 * 8;
+                                  (size_t)TEAMS * 3 * L * 2 * sizeof(T) + NSUM * (size_t)TEAMS * TPF * sizeof(T) + 16 * 5 * 8;
   static constexpr bool value = bytes <= 150 * 1024;
 };
 
@@ -312,7 +314,8 @@ __device__ __forceinline__ void stage_copy(cx<T>* __restrict__ g, cx<T>* __restr
 //             stress and tau; per-step outputs and sums of the strain
 //   ROW_FWD / ROW_INV  plain row transforms of three real planes (checks)
 template <typename T, int L, int RMAX, int TEAMS, int WT, int MODE>
-__global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_ROW_WPE))) k_row(RowArgs<T> a) {
+__global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_ROW_WPE)))
+k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   constexpr int TPF = L / RMAX;
   constexpr int BS = TEAMS * TPF;
   constexpr int LS = LdsSize<L>::value;
@@ -321,7 +324,9 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
   constexpr bool POINTWISE = MODE == ROW_ITER || MODE == ROW_INIT;
   constexpr bool STAGED = RowStage<T, L, TEAMS, TPF>::value;
   constexpr int GSTRIDE = L * WT * 3, SSTRIDE = 2 * WT * 3;
-  if (a.state && a.state->halted) return;
+  constexpr int BPS = (L / 2) / TEAMS;                 // blocks per slot
+  const Slot<T>& S = slots[blockIdx.x / BPS];
+  if (gated_out(x, S.st)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int team = threadIdx.x / TPF;
   const int t = threadIdx.x % TPF;
@@ -329,12 +334,12 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
   T* lim = lre + LS;
   // LDS stage of this team's row pair: 3 L complex values after the FFT buffers
   cx<T>* stg = reinterpret_cast<cx<T>*>(reinterpret_cast<T*>(smem_raw) + TEAMS * 2 * LS) + team * 3 * L;
-  const int p = xcd_remap(blockIdx.x, gridDim.x) * TEAMS + team;
+  const int p = xcd_remap(blockIdx.x % BPS, BPS) * TEAMS + team;
   const int ra = 2 * p, rb = 2 * p + 1;
-  cx<T>* __restrict__ spec = a.spec;
+  cx<T>* __restrict__ spec = S.spec;
   cx<T>* __restrict__ gbase = spec + (size_t)ra * WT * 3;
-  const cx<T>* __restrict__ tw = a.tw;
-  const Mat<T> m = make_mat<T>(a.prm);
+  const cx<T>* __restrict__ tw = S.tw;
+  const Mat<T> m = make_mat<T>(S.prm);
   constexpr unsigned NPX = (unsigned)L * L;
 
   cx<T> za[RMAX], zb[RMAX], zc[RMAX];
@@ -349,10 +354,10 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const unsigned ix = (unsigned)(half ? rb : ra) * L + t + TPF * s;
-      mk[s][half] = a.mask[ix];
+      mk[s][half] = S.mask[ix];
       if constexpr (MODE == ROW_ITER) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) so[s][half][c] = a.sig[c * NPX + ix];
+        for (int c = 0; c < 4; ++c) so[s][half][c] = S.sig[c * NPX + ix];
       }
     }
   };
@@ -396,8 +401,8 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
     for (int s = 0; s < RMAX; ++s) {
       const int x1 = t + TPF * s;
       const unsigned ia = (unsigned)ra * L + x1, ib = (unsigned)rb * L + x1;
-      a.real_out[ia] = za[s].re; a.real_out[NPX + ia] = za[s].im; a.real_out[2 * NPX + ia] = zc[s].re;
-      a.real_out[ib] = zb[s].re; a.real_out[NPX + ib] = zb[s].im; a.real_out[2 * NPX + ib] = zc[s].im;
+      x.real_out[ia] = za[s].re; x.real_out[NPX + ia] = za[s].im; x.real_out[2 * NPX + ia] = zc[s].re;
+      x.real_out[ib] = zb[s].re; x.real_out[NPX + ib] = zb[s].im; x.real_out[2 * NPX + ib] = zc[s].im;
     }
     return;
   }
@@ -412,29 +417,29 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
-        const bool isv = a.mask[ix] != 0;
+        const bool isv = S.mask[ix] != 0;
         T tau[3];
         if (half == 0) { tau[0] = za[s].re * invL; tau[1] = za[s].im * invL; tau[2] = zc[s].re * invL; }
         else { tau[0] = zb[s].re * invL; tau[1] = zb[s].im * invL; tau[2] = zc[s].im * invL; }
-        T sg[4] = {a.sig[ix], a.sig[NPX + ix], a.sig[2 * NPX + ix], a.sig[3 * NPX + ix]};
+        T sg[4] = {S.sig[ix], S.sig[NPX + ix], S.sig[2 * NPX + ix], S.sig[3 * NPX + ix]};
         T en[4];
         strain_from(sg, tau, isv, m, en);
         T dummy[4];
         const bool pl = !isv && hencky(en, dummy, m);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] += (double)en[c];
-        if (a.sig_out) {
+        if (x.sig_out) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) a.sig_out[c * NPX + ix] = sg[c];
+          for (int c = 0; c < 4; ++c) x.sig_out[c * NPX + ix] = sg[c];
         }
-        if (a.eps_out) {
+        if (x.eps_out) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) a.eps_out[c * NPX + ix] = en[c];
+          for (int c = 0; c < 4; ++c) x.eps_out[c * NPX + ix] = en[c];
         }
-        if (a.plastic_out) a.plastic_out[ix] = pl ? 1 : 0;
+        if (x.plastic_out) x.plastic_out[ix] = pl ? 1 : 0;
       }
     }
-    block_reduce_store<4>(acc, a.partials + (size_t)blockIdx.x * 4);
+    block_reduce_store<4>(acc, S.part2 + (size_t)(blockIdx.x % BPS) * 4);
     return;
   }
 
@@ -443,9 +448,9 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
     for (int s = 0; s < RMAX; ++s) {
       const int x1 = t + TPF * s;
       const unsigned ia = (unsigned)ra * L + x1, ib = (unsigned)rb * L + x1;
-      za[s] = {a.real_in[ia], a.real_in[NPX + ia]};
-      zb[s] = {a.real_in[ib], a.real_in[NPX + ib]};
-      zc[s] = {a.real_in[2 * NPX + ia], a.real_in[2 * NPX + ib]};
+      za[s] = {x.real_in[ia], x.real_in[NPX + ia]};
+      zb[s] = {x.real_in[ib], x.real_in[NPX + ib]};
+      zc[s] = {x.real_in[2 * NPX + ia], x.real_in[2 * NPX + ib]};
     }
   }
 
@@ -454,11 +459,13 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
     // (sigma 11, 22, 33, 12 and |e - eps|^2) are kept in LDS rather than
     // registers, which keeps the kernel free of spills; block and global
     // sums are FP64.
-    __shared__ T lacc[5][BS];
-    T* __restrict__ sig = a.sig;
-    const T E0 = (T)a.E[0], E1 = (T)a.E[1], E2 = (T)a.E[2];
+    __shared__ T lacc[NSUM][BS];
+    T* __restrict__ sig = S.sig;
+    // ROW_INIT: the load step's E from the slot state, or from the arguments
+    const double* Ed = x.use_state ? S.st->E : x.E;
+    const T E0 = (T)Ed[0], E1 = (T)Ed[1], E2 = (T)Ed[2];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lacc[i][threadIdx.x] = (T)0;
+    for (int i = 0; i < NSUM; ++i) lacc[i][threadIdx.x] = (T)0;
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
       const int x1 = t + TPF * s;
@@ -468,13 +475,14 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
         const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
         const bool isv = mk[s][half] != 0;
         T e[3], en[4], sg[4], tau[3];
+        bool pl = false;
         if constexpr (MODE == ROW_INIT) {
           e[0] = E0; e[1] = E1; e[2] = E2;
           en[0] = E0; en[1] = E1; en[2] = (T)0; en[3] = E2;
           if (isv) {
             sg[0] = sg[1] = sg[2] = sg[3] = (T)0;
           } else {
-            hencky(en, sg, m);
+            pl = hencky(en, sg, m);
           }
           const T c0t = m.lam0 * (E0 + E1);
           tau[0] = sg[0] - (c0t + (T)2 * m.mu0 * E0);
@@ -483,14 +491,15 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
         } else {
           if (half == 0) { e[0] = za[s].re; e[1] = za[s].im; e[2] = zc[s].re; }
           else { e[0] = zb[s].re; e[1] = zb[s].im; e[2] = zc[s].im; }
-          alm_point(e, so[s][half], isv, m, en, sg, tau);
+          pl = alm_point(e, so[s][half], isv, m, en, sg, tau);
         }
         sig[ix] = sg[0]; sig[NPX + ix] = sg[1]; sig[2 * NPX + ix] = sg[2]; sig[3 * NPX + ix] = sg[3];
         {
           const T c0 = e[0] - en[0], c1 = e[1] - en[1], c2 = en[2], c3 = e[2] - en[3];
-          const T v5[5] = {sg[0], sg[1], sg[2], sg[3], c0 * c0 + c1 * c1 + c2 * c2 + (T)2 * c3 * c3};
+          const T v6[NSUM] = {sg[0], sg[1], sg[2], sg[3], c0 * c0 + c1 * c1 + c2 * c2 + (T)2 * c3 * c3,
+                              pl ? (T)1 : (T)0};
 #pragma unroll
-          for (int i = 0; i < 5; ++i) lacc[i][threadIdx.x] += v5[i];
+          for (int i = 0; i < NSUM; ++i) lacc[i][threadIdx.x] += v6[i];
         }
         if (half == 0) { za[s] = {tau[0], tau[1]}; zc[s].re = tau[2]; }
         else { zb[s] = {tau[0], tau[1]}; zc[s].im = tau[2]; }
@@ -498,10 +507,10 @@ __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_
       __builtin_amdgcn_sched_barrier(0);
     }
     fence(za); fence(zb); fence(zc);
-    double accd[5];
+    double accd[NSUM];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) accd[i] = (double)lacc[i][threadIdx.x];
-    block_reduce_store<5>(accd, a.partials + (size_t)blockIdx.x * NPART);
+    for (int i = 0; i < NSUM; ++i) accd[i] = (double)lacc[i][threadIdx.x];
+    block_reduce_store<NSUM>(accd, S.part + (size_t)(blockIdx.x % BPS) * NPART);
   }
 
   fft<-1, T, L, RMAX>(za, lre, lim, t, tw);
@@ -555,19 +564,19 @@ __device__ __forceinline__ void green_apply(cx<T>* tt, cx<T> k1, cx<T> k2, const
 
 // Green tensor at momentum (m1, m2), or E at q = 0.
 template <typename T>
-__device__ __forceinline__ void green_at(cx<T>* tt, int m1, int m2, const ColArgs<T>& a, const T lam0, const T mu0,
-                                         const T scale) {
+__device__ __forceinline__ void green_at(cx<T>* tt, int m1, int m2, const Slot<T>& S, const Extra<T>& x,
+                                         const T lam0, const T mu0, const T scale) {
   if (m1 == 0 && m2 == 0) {
-    double E0 = a.E[0], E1 = a.E[1], E2 = a.E[2];
-    if (a.state) { E0 = a.state->E[0]; E1 = a.state->E[1]; E2 = a.state->E[2]; }
+    double E0 = x.E[0], E1 = x.E[1], E2 = x.E[2];
+    if (x.use_state) { E0 = S.st->E[0]; E1 = S.st->E[1]; E2 = S.st->E[2]; }
     tt[0] = {(T)E0, (T)0};
     tt[1] = {(T)E1, (T)0};
     tt[2] = {(T)E2, (T)0};
     return;
   }
-  cx<T> k1 = a.ktab[m1], k2 = a.ktab[m2];
-  if (a.flip1) k1 = {-k1.re, k1.im};   // k(-q) = -conj(k(q))
-  if (a.flip2) k2 = {-k2.re, k2.im};
+  cx<T> k1 = S.ktab[m1], k2 = S.ktab[m2];
+  if (S.flip1) k1 = {-k1.re, k1.im};   // k(-q) = -conj(k(q))
+  if (S.flip2) k2 = {-k2.re, k2.im};
   green_apply(tt, k1, k2, lam0, mu0, scale);
 }
 
@@ -578,20 +587,23 @@ __device__ __forceinline__ void green_at(cx<T>* tt, int m1, int m2, const ColArg
 // with conj-symmetry into the two real-signal spectra, each gets its own
 // Green tensor, and the results are packed again before the inverse.
 template <typename T, int L, int RMAX, int W, int MODE>
-__global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_COL_WPE))) k_column(ColArgs<T> a) {
+__global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_COL_WPE)))
+k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
   constexpr int TPF = L / RMAX;
   constexpr int LS = LdsSize<L>::value;
-  if (a.state && a.state->halted) return;
+  constexpr int BPS = (L / 2) / W;                     // blocks (tiles) per slot
+  const Slot<T>& S = slots[blockIdx.x / BPS];
+  if (gated_out(x, S.st)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int w = threadIdx.x % W;
   const int t = threadIdx.x / W;
   T* lre = reinterpret_cast<T*>(smem_raw) + w * 2 * LS;
   T* lim = lre + LS;
-  const int g = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = xcd_remap(blockIdx.x % BPS, BPS);
   const int m1 = g * W + w;
   const bool packed = (g == 0);           // block-uniform: tile 0 holds column 0
-  cx<T>* __restrict__ spec = a.spec;
-  const cx<T>* __restrict__ tw = a.tw;
+  cx<T>* __restrict__ spec = S.spec;
+  const cx<T>* __restrict__ tw = S.tw;
   cx<T>* __restrict__ tile = spec + (size_t)g * L * W * 3;
 
   cx<T> v[3][RMAX];
@@ -606,7 +618,7 @@ __global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_
     for (int c = 0; c < 3; ++c) fft<-1, T, L, RMAX>(v[c], lre, lim, t, tw);
   }
   if constexpr ((MODE & COL_GREEN) != 0) {
-    const T lam0 = (T)a.lam0, mu0 = (T)a.mu0, scale = (T)a.scale;
+    const T lam0 = (T)S.prm.lam0, mu0 = (T)S.prm.mu0, scale = (T)x.scale;
     if (packed) {
       // Column 0 (bins m1 = 0 and L/2 packed) passes its transform through a
       // small global buffer to read the partners conj Z[L - m2]; the branch is
@@ -616,7 +628,7 @@ __global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int s = 0; s < RMAX; ++s) a.xbuf[c * L + t + TPF * s] = v[c][s];
+          for (int s = 0; s < RMAX; ++s) S.xbuf[c * L + t + TPF * s] = v[c][s];
       }
       __threadfence_block();
       __syncthreads();
@@ -628,13 +640,13 @@ __global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_
           cx<T> x0[3], xn[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const cx<T> zr = cconj(a.xbuf[c * L + mr]);
+            const cx<T> zr = cconj(S.xbuf[c * L + mr]);
             const cx<T> d = v[c][s] - zr;
             x0[c] = cscale(v[c][s] + zr, (T)0.5);
             xn[c] = {d.im * (T)0.5, -d.re * (T)0.5};
           }
-          green_at(x0, 0, m2, a, lam0, mu0, scale);
-          green_at(xn, L / 2, m2, a, lam0, mu0, scale);
+          green_at(x0, 0, m2, S, x, lam0, mu0, scale);
+          green_at(xn, L / 2, m2, S, x, lam0, mu0, scale);
 #pragma unroll
           for (int c = 0; c < 3; ++c) v[c][s] = {x0[c].re - xn[c].im, x0[c].im + xn[c].re};
         }
@@ -645,7 +657,7 @@ __global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_
       for (int s = 0; s < RMAX; ++s) {
         const int m2 = t + TPF * s;
         cx<T> tt[3] = {v[0][s], v[1][s], v[2][s]};
-        green_at(tt, m1, m2, a, lam0, mu0, scale);
+        green_at(tt, m1, m2, S, x, lam0, mu0, scale);
         v[0][s] = tt[0]; v[1][s] = tt[1]; v[2][s] = tt[2];
       }
     }
@@ -696,7 +708,7 @@ static size_t col_lds() {
 }
 
 template <typename T, int L, int MODE>
-static hipError_t launch_row_LM(const RowArgs<T>& a, hipStream_t st) {
+static hipError_t launch_row_LM(const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
   using C = Cfg<T, L>;
   auto kern = k_row<T, L, C::RMAX, C::ROW_TEAMS, C::COL_W, MODE>;
   static bool attr = false;
@@ -706,13 +718,13 @@ static hipError_t launch_row_LM(const RowArgs<T>& a, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const int grid = (L / 2) / C::ROW_TEAMS;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::ROW_TEAMS * C::TPF), lds, st, a);
+  const int grid = nslots * ((L / 2) / C::ROW_TEAMS);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::ROW_TEAMS * C::TPF), lds, st, slots, x);
   return hipGetLastError();
 }
 
 template <typename T, int L, int MODE>
-static hipError_t launch_col_LM(const ColArgs<T>& a, hipStream_t st) {
+static hipError_t launch_col_LM(const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
   using C = Cfg<T, L>;
   auto kern = k_column<T, L, C::COL_RMAX, C::COL_W, MODE>;
   static bool attr = false;
@@ -722,30 +734,30 @@ static hipError_t launch_col_LM(const ColArgs<T>& a, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const int grid = (L / 2) / C::COL_W;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::COL_W * C::COL_TPF), lds, st, a);
+  const int grid = nslots * ((L / 2) / C::COL_W);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::COL_W * C::COL_TPF), lds, st, slots, x);
   return hipGetLastError();
 }
 
 template <typename T, int L>
-static hipError_t launch_row_L(const RowArgs<T>& a, hipStream_t st) {
-  switch (a.mode) {
-    case ROW_ITER: return launch_row_LM<T, L, ROW_ITER>(a, st);
-    case ROW_INIT: return launch_row_LM<T, L, ROW_INIT>(a, st);
-    case ROW_FWD: return launch_row_LM<T, L, ROW_FWD>(a, st);
-    case ROW_INV: return launch_row_LM<T, L, ROW_INV>(a, st);
-    case ROW_EMIT: return launch_row_LM<T, L, ROW_EMIT>(a, st);
+static hipError_t launch_row_L(int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
+  switch (mode) {
+    case ROW_ITER: return launch_row_LM<T, L, ROW_ITER>(slots, nslots, x, st);
+    case ROW_INIT: return launch_row_LM<T, L, ROW_INIT>(slots, nslots, x, st);
+    case ROW_FWD: return launch_row_LM<T, L, ROW_FWD>(slots, nslots, x, st);
+    case ROW_INV: return launch_row_LM<T, L, ROW_INV>(slots, nslots, x, st);
+    case ROW_EMIT: return launch_row_LM<T, L, ROW_EMIT>(slots, nslots, x, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int L>
-static hipError_t launch_col_L(const ColArgs<T>& a, hipStream_t st) {
-  switch (a.mode) {
-    case COL_ALL: return launch_col_LM<T, L, COL_ALL>(a, st);
-    case COL_FWD: return launch_col_LM<T, L, COL_FWD>(a, st);
-    case COL_INV: return launch_col_LM<T, L, COL_INV>(a, st);
-    case COL_GREEN: return launch_col_LM<T, L, COL_GREEN>(a, st);
+static hipError_t launch_col_L(int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
+  switch (mode) {
+    case COL_ALL: return launch_col_LM<T, L, COL_ALL>(slots, nslots, x, st);
+    case COL_FWD: return launch_col_LM<T, L, COL_FWD>(slots, nslots, x, st);
+    case COL_INV: return launch_col_LM<T, L, COL_INV>(slots, nslots, x, st);
+    case COL_GREEN: return launch_col_LM<T, L, COL_GREEN>(slots, nslots, x, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -773,12 +785,12 @@ static int tile_w_L() { return Cfg<T, L>::COL_W; }
   }
 
 template <typename T>
-hipError_t launch_row(int L, const RowArgs<T>& a, hipStream_t st) {
-  PM_DISPATCH_L(launch_row_L, T, L, a, st)
+hipError_t launch_row(int L, int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
+  PM_DISPATCH_L(launch_row_L, T, L, mode, slots, nslots, x, st)
 }
 template <typename T>
-hipError_t launch_col(int L, const ColArgs<T>& a, hipStream_t st) {
-  PM_DISPATCH_L(launch_col_L, T, L, a, st)
+hipError_t launch_col(int L, int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
+  PM_DISPATCH_L(launch_col_L, T, L, mode, slots, nslots, x, st)
 }
 
 #define PM_DISPATCH_INT(FN, T, L)     \
@@ -799,7 +811,7 @@ hipError_t launch_col(int L, const ColArgs<T>& a, hipStream_t st) {
   }
 
 template <typename T>
-int row_grid(int L) {
+int row_blocks(int L) {
   PM_DISPATCH_INT(row_grid_L, T, L)
 }
 template <typename T>

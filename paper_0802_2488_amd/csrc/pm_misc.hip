@@ -1,36 +1,71 @@
-// Reductions, convergence logic, residual, outputs and the mask generator.
+// Reductions, convergence logic, equilibrium residual, output sums and the
+// mask generator.  One block per slot for the final reductions.
 #include "pm_kernels.hpp"
 
 namespace pm {
 
-// ---------------------------------------------------------------------------
-// Reductions and convergence logic (one block of 256 threads).
 __device__ __forceinline__ double norm4(const double* a) {
   return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + 2.0 * a[3] * a[3]);
 }
 
-__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partials, int nblk, DevState* st,
-                                                DevParams prm) {
+// Start a load step at E (also used when the device advances the ramp).
+__device__ __forceinline__ void begin_step(DevState* st, double E0, double E1, double E2, double mu) {
+  st->E[0] = E0; st->E[1] = E1; st->E[2] = E2;
+  st->normE = sqrt(E0 * E0 + E1 * E1 + 2.0 * E2 * E2);
+  st->floor_s = 1e-12 * mu * st->normE;
+  st->iter = 0; st->halted = 0; st->status = ST_RUNNING; st->need_eq = 0;
+  st->res_eq = st->res_mac = st->res_cmp = INFINITY;
+}
+
+// A load step ended with `status`.  The slot halts.  Without a device ramp
+// the host reads the state; with one, the step's record is written and
+// marked pending: the output pass adds <eps> to it and the advance kernel
+// starts the next step from the current state.
+template <typename T>
+__device__ __forceinline__ void end_step(DevState* st, const Slot<T>& S, int status) {
+  st->status = status;
+  st->halted = 1;
+  if (S.rec == nullptr || S.E_path == nullptr) return;
+  StepRecord r;
+  for (int i = 0; i < 4; ++i) {
+    r.sm[i] = st->sm[i];
+    r.em[i] = 0.0;
+  }
+  r.res_eq = st->res_eq; r.res_mac = st->res_mac; r.res_cmp = st->res_cmp;
+  r.plastic = st->plastic;
+  r.iters = st->iter; r.status = status;
+  S.rec[st->step] = r;
+  st->pending = 1;
+}
+
+// Sum the row-pass partials of one slot (fixed order), update <sigma>, the
+// change indicator eta_2 and the constraint indicator; decide whether the
+// equilibrium indicator must be evaluated this iteration.
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce(const Slot<T>* __restrict__ slots, int nblk) {
+  const Slot<T>& S = slots[blockIdx.x];
+  DevState* st = S.st;
   if (st->halted) return;
-  __shared__ double red[256][5];
-  double s[5];
+  __shared__ double red[256][NSUM];
+  double s[NSUM];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) s[i] = 0.0;
+  for (int i = 0; i < NSUM; ++i) s[i] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 256) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) s[i] += partials[(long)b * NPART + i];
+    for (int i = 0; i < NSUM; ++i) s[i] += S.part[(long)b * NPART + i];
   }
 #pragma unroll
-  for (int i = 0; i < 5; ++i) red[threadIdx.x][i] = s[i];
+  for (int i = 0; i < NSUM; ++i) red[threadIdx.x][i] = s[i];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) {
 #pragma unroll
-      for (int i = 0; i < 5; ++i) red[threadIdx.x][i] += red[threadIdx.x + off][i];
+      for (int i = 0; i < NSUM; ++i) red[threadIdx.x][i] += red[threadIdx.x + off][i];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    const DevParams& prm = S.prm;
     const double inv = 1.0 / prm.npx;
     double sm[4], dsm[4];
     for (int i = 0; i < 4; ++i) {
@@ -49,35 +84,35 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
     st->res_cmp = rcmp;
     st->res_mac = rmac;
     st->res_eq = INFINITY;
+    st->plastic = red[0][5] * inv;
     bool bad = false;
-    for (int i = 0; i < 5; ++i) bad |= !isfinite(red[0][i]);
+    for (int i = 0; i < NSUM; ++i) bad |= !isfinite(red[0][i]);
     if (bad) {
-      st->status = ST_NAN;
-      st->halted = 1;
       st->need_eq = 0;
+      end_step(st, S, ST_NAN);
       return;
     }
-    const int need = (it >= 2 && rmac < prm.eta_mac && rcmp < prm.eta_cmp) ? 1 : 0;
+    // 1: all other tests pass, so test equilibrium; 2: the last iteration
+    // allowed, evaluate the equilibrium indicator only for the record.
+    int need = (it >= 2 && rmac < prm.eta_mac && rcmp < prm.eta_cmp) ? 1 : 0;
+    if (!need && it >= prm.max_iter) need = 2;
     st->need_eq = need;
-    if (!need && it >= prm.max_iter) {
-      st->status = ST_NOCONV;
-      st->halted = 1;
-    }
   }
 }
 
 // Backward-difference divergence of eq. 1 of the stored stress:
 // div_i(x) = sum_j sigma_ij(x) - sigma_ij(x - e^j), direction 1 = x1.
 template <typename T>
-__global__ void __launch_bounds__(256) k_div(const T* __restrict__ sig, double* __restrict__ partials,
-                                             const DevState* st, int L, int force) {
-  if (!force && (st->halted || !st->need_eq)) return;
+__global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, int L, int dbps, int force) {
+  const Slot<T>& S = slots[blockIdx.x / dbps];
+  const int lb = blockIdx.x % dbps;
+  if (!force && (S.st->halted || !S.st->need_eq)) return;
   const long npx = (long)L * L;
-  const T* __restrict__ s11 = sig;
-  const T* __restrict__ s22 = sig + npx;
-  const T* __restrict__ s12 = sig + 3 * npx;
+  const T* __restrict__ s11 = S.sig;
+  const T* __restrict__ s22 = S.sig + npx;
+  const T* __restrict__ s12 = S.sig + 3 * npx;
   double acc[1] = {0.0};
-  for (long ix = (long)blockIdx.x * blockDim.x + threadIdx.x; ix < npx; ix += (long)gridDim.x * blockDim.x) {
+  for (long ix = (long)lb * blockDim.x + threadIdx.x; ix < npx; ix += (long)dbps * blockDim.x) {
     const int x1 = (int)(ix & (L - 1));
     const int x2 = (int)(ix / L);
     const long i1 = (long)x2 * L + ((x1 + L - 1) & (L - 1));   // x - e^1
@@ -86,15 +121,19 @@ __global__ void __launch_bounds__(256) k_div(const T* __restrict__ sig, double* 
     const double d2 = ((double)s12[ix] - (double)s12[i1]) + ((double)s22[ix] - (double)s22[i2]);
     acc[0] += d1 * d1 + d2 * d2;
   }
-  block_reduce_store<1>(acc, partials + blockIdx.x);
+  block_reduce_store<1>(acc, S.part2 + lb);
 }
 
-__global__ void __launch_bounds__(256) k_reduce_div(const double* __restrict__ partials, int nblk, DevState* st,
-                                                    DevParams prm, int force) {
+// Equilibrium indicator eta_1 from the residual partials; ends the step on
+// convergence or at max_iter.  force: only record the indicator.
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce_div(const Slot<T>* __restrict__ slots, int nblk, int force) {
+  const Slot<T>& S = slots[blockIdx.x];
+  DevState* st = S.st;
   if (!force && (st->halted || !st->need_eq)) return;
   __shared__ double red[256];
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 256) s += partials[b];
+  for (int b = threadIdx.x; b < nblk; b += 256) s += S.part2[b];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
@@ -103,40 +142,26 @@ __global__ void __launch_bounds__(256) k_reduce_div(const double* __restrict__ p
   }
   if (threadIdx.x == 0) {
     const double ns = fmax(norm4(st->sm), st->floor_s);
-    const double req = sqrt(red[0] / prm.npx) / ns;
+    const double req = sqrt(red[0] / S.prm.npx) / ns;
     st->res_eq = req;
     if (force) return;
-    if (!isfinite(red[0])) {
-      st->status = ST_NAN;
-      st->halted = 1;
-    } else if (req < prm.eta_eq) {
-      st->status = ST_CONVERGED;
-      st->halted = 1;
-    } else if (st->iter >= prm.max_iter) {
-      st->status = ST_NOCONV;
-      st->halted = 1;
-    }
+    if (!isfinite(red[0])) end_step(st, S, ST_NAN);
+    else if (st->need_eq == 1 && req < S.prm.eta_eq) end_step(st, S, ST_CONVERGED);
+    else if (st->iter >= S.prm.max_iter) end_step(st, S, ST_NOCONV);
   }
 }
 
-__global__ void k_begin(DevState* st, double E0, double E1, double E2, double floor_s) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->E[0] = E0; st->E[1] = E1; st->E[2] = E2;
-    st->normE = sqrt(E0 * E0 + E1 * E1 + 2.0 * E2 * E2);
-    st->floor_s = floor_s;
-    st->iter = 0; st->halted = 0; st->status = ST_RUNNING; st->need_eq = 0;
-    st->res_eq = st->res_mac = st->res_cmp = INFINITY;
-  }
-}
-
-// Final FP64 reduction of the per-block strain sums written by the output pass.
-__global__ void __launch_bounds__(256) k_reduce_emit(const double* __restrict__ partials, int nblk, DevState* st,
-                                                     double npx) {
+// <eps> from the output pass's per-block sums; with gate GATE_PENDING only
+// for slots whose step record waits for it, and into that record too.
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce_emit(const Slot<T>* __restrict__ slots, int nblk, int gate) {
+  const Slot<T>& S = slots[blockIdx.x];
+  if (gate == GATE_PENDING && !S.st->pending) return;
   __shared__ double red[256][4];
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += 256) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s[i] += partials[(long)b * 4 + i];
+    for (int i = 0; i < 4; ++i) s[i] += S.part2[(long)b * 4 + i];
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) red[threadIdx.x][i] = s[i];
@@ -149,7 +174,40 @@ __global__ void __launch_bounds__(256) k_reduce_emit(const double* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    for (int i = 0; i < 4; ++i) st->em[i] = red[0][i] / npx;
+    DevState* st = S.st;
+    for (int i = 0; i < 4; ++i) st->em[i] = red[0][i] / S.prm.npx;
+    if (gate == GATE_PENDING && S.rec != nullptr) {
+      for (int i = 0; i < 4; ++i) S.rec[st->step].em[i] = st->em[i];
+    }
+  }
+}
+
+// Move every slot with a pending record to the next load step of its ramp
+// (the current state is the warm start), or mark it finished.
+template <typename T>
+__global__ void k_advance(const Slot<T>* __restrict__ slots, int nslots) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nslots) return;
+  const Slot<T>& S = slots[i];
+  DevState* st = S.st;
+  if (!st->pending) return;
+  st->pending = 0;
+  const int next = st->step + 1;
+  if (st->status == ST_NAN || next >= st->nsteps) {
+    st->finished = 1;
+    return;
+  }
+  st->step = next;
+  begin_step(st, S.E_path[3 * next], S.E_path[3 * next + 1], S.E_path[3 * next + 2], S.prm.mu);
+}
+
+__global__ void k_begin(DevState* st, double E0, double E1, double E2, double mu, int32_t step, int32_t nsteps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    begin_step(st, E0, E1, E2, mu);
+    st->step = step;
+    st->nsteps = nsteps;
+    st->finished = 0;
+    st->pending = 0;
   }
 }
 
@@ -169,39 +227,53 @@ __global__ void __launch_bounds__(256) k_mask(uint8_t* __restrict__ out, long np
   }
 }
 
-
-int div_grid(int L) {
+// ---------------------------------------------------------------------------
+int div_blocks(int L) {
   const long npx = (long)L * L;
   long g = (npx + 255) / 256;
-  if (g > 4096) g = 4096;
+  if (g > 1024) g = 1024;
   return (int)g;
 }
 
-hipError_t launch_reduce(const double* partials, int nblk, DevState* st, const DevParams& prm, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nblk, st, prm);
+template <typename T>
+hipError_t launch_reduce(const Slot<T>* slots, int nslots, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce<T>, dim3(nslots), dim3(256), 0, s, slots, nblk);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_div(const T* sig, double* partials, DevState* st, const DevParams& prm, int L, int force,
-                      hipStream_t s) {
-  const int g = div_grid(L);
-  hipLaunchKernelGGL(k_div<T>, dim3(g), dim3(256), 0, s, sig, partials, st, L, force);
+hipError_t launch_div(const Slot<T>* slots, int nslots, int L, int force, hipStream_t s) {
+  const int g = div_blocks(L);
+  hipLaunchKernelGGL(k_div<T>, dim3(nslots * g), dim3(256), 0, s, slots, L, g, force);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_div, dim3(1), dim3(256), 0, s, partials, g, st, prm, force);
-  return hipGetLastError();
-}
-template hipError_t launch_div<float>(const float*, double*, DevState*, const DevParams&, int, int, hipStream_t);
-template hipError_t launch_div<double>(const double*, double*, DevState*, const DevParams&, int, int, hipStream_t);
-
-hipError_t launch_begin(DevState* st, const double* E, double floor_s, hipStream_t s) {
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, st, E[0], E[1], E[2], floor_s);
+  hipLaunchKernelGGL(k_reduce_div<T>, dim3(nslots), dim3(256), 0, s, slots, g, force);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_emit(const double* partials, int nblk, DevState* st, double npx, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_emit, dim3(1), dim3(256), 0, s, partials, nblk, st, npx);
+template <typename T>
+hipError_t launch_reduce_emit(const Slot<T>* slots, int nslots, int nblk, int gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_emit<T>, dim3(nslots), dim3(256), 0, s, slots, nblk, gate);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_advance(const Slot<T>* slots, int nslots, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance<T>, dim3((nslots + 63) / 64), dim3(64), 0, s, slots, nslots);
+  return hipGetLastError();
+}
+
+#define PM_INST(T)                                                                     \
+  template hipError_t launch_reduce<T>(const Slot<T>*, int, int, hipStream_t);        \
+  template hipError_t launch_div<T>(const Slot<T>*, int, int, int, hipStream_t);      \
+  template hipError_t launch_reduce_emit<T>(const Slot<T>*, int, int, int, hipStream_t); \
+  template hipError_t launch_advance<T>(const Slot<T>*, int, hipStream_t);
+PM_INST(float)
+PM_INST(double)
+#undef PM_INST
+
+hipError_t launch_begin(DevState* st, const double* E, double mu, int32_t step, int32_t nsteps, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, st, E[0], E[1], E[2], mu, step, nsteps);
   return hipGetLastError();
 }
 
