@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -40,6 +42,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (reference for HBM byte counters)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-realization workload")
+    ap.add_argument("--batch-n", type=int, default=256)
+    ap.add_argument("--batch-max-iter", type=int, default=500)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-n", type=int, default=64, help="requests of the serving trace (200 = full trace)")
+    ap.add_argument("--serve-max-iter", type=int, default=200)
+    ap.add_argument("--serve-pool-gb", type=float, default=16.0)
+    ap.add_argument("--tick", type=int, default=16, help="iterations per batch tick")
     return ap.parse_args()
 
 
@@ -109,6 +119,106 @@ def run_gpu(L, precision, steps, warmup, max_iter, timing=True):
     return dict(value=L * L * iters / dt, seconds=dt, iters=iters, info=info, timing=tm)
 
 
+def batch_jobs(n, max_iter):
+    """The uneven batched workload: masks on the device, FP32, tol 1e-6."""
+    from paper_0802_2488_amd import solver as pms
+    from paper_0802_2488_amd import synth
+
+    jobs = []
+    for r in synth.batch_realizations(n):
+        mask = pms.device_mask(r["L"], r["f"], r["seed"])
+        params = pms.make_params(r["L"], mu=1.0, lam=2.0, Y=1.0, tol=1e-6, max_iter=max_iter, precision="fp32")
+        path = synth.load_path(r["kind"], r["steps"], synth.default_emax(r["kind"], 1.0, 1.0))
+        jobs.append((mask, params, path))
+    return jobs
+
+
+def run_batch(jobs, tick):
+    import torch
+
+    from paper_0802_2488_amd import batch as pmb
+
+    pool = pmb.overhead_bytes(len(jobs)) + sum(pmb.slot_bytes(p, len(path)) for _, p, path in jobs)
+    b = pmb.Batch(pool, max_slots=len(jobs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = pmb.run_all(b, jobs, tick_iters=tick)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    work = sum(j[1].L ** 2 * sum(r.iters for r in rr) for j, rr in zip(jobs, recs))
+    return dict(value=work / dt, seconds=dt, pixel_iters=work, pool_bytes=pool,
+                converged_steps=sum(r.status == 1 for rr in recs for r in rr),
+                steps=sum(len(rr) for rr in recs))
+
+
+def run_sequential(jobs):
+    import torch
+
+    from paper_0802_2488_amd import solver as pms
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    work = 0
+    for mask, params, path in jobs:
+        s = pms.Solver(mask, params)
+        for E in path:
+            work += params.L ** 2 * s.step(E, fields=False).iters
+        s.close()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(value=work / dt, seconds=dt, pixel_iters=work)
+
+
+def batched_section(a):
+    jobs = batch_jobs(a.batch_n, a.batch_max_iter)
+    full = run_batch(jobs, a.tick)
+    print(f"# batched done: {full['value']:.4e} px-iter/s in {full['seconds']:.1f} s", file=sys.stderr, flush=True)
+    # same-work comparison on a sample: 16 realizations x their first 3 load steps
+    sample = [(m, p, path[:3]) for m, p, path in jobs[:16]]
+    sb = run_batch(sample, a.tick)
+    sq = run_sequential(sample)
+    print(f"# sequential sample done: {sq['value']:.4e} px-iter/s", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{a.batch_n} realizations (seed 1000 + r, L uniform on {{128, 256, 512}}, f ~ U[0.05, 0.4], "
+                    f"even r equibiaxial to 3Y/mu, odd r shear to 4Y/mu, 20 load steps, tol 1e-6, FP32, "
+                    f"max_iter {a.batch_max_iter}), one batch, {a.tick} iterations per tick",
+        "value": full["value"], "unit": "pixel-iters/s", "seconds": full["seconds"],
+        "pixel_iters": full["pixel_iters"], "steps": full["steps"], "converged_steps": full["converged_steps"],
+        "pool_bytes": full["pool_bytes"],
+        "same_work_sample": {"what": "realizations 0-15, load steps 1-3",
+                             "batched": sb["value"], "sequential": sq["value"],
+                             "speedup": sb["value"] / sq["value"]},
+    }
+
+
+def serving_section(a):
+    from paper_0802_2488_amd import serve, synth
+
+    pool = int(a.serve_pool_gb * (1 << 30))
+    base = synth.serving_trace(a.serve_n, 7, 1.0)
+    # capacity: the same requests all present at t = 0
+    _, w_cap, wall_cap, _ = serve.serve_batched(base, pool_bytes=pool, tick_iters=a.tick,
+                                                max_iter=a.serve_max_iter, ignore_arrivals=True)
+    cap = a.serve_n / wall_cap
+    rate = 0.8 * cap
+    print(f"# serving capacity {cap:.2f} req/s; arrivals at {rate:.2f} req/s", file=sys.stderr, flush=True)
+    trace = synth.serving_trace(a.serve_n, 7, rate)
+    lat_b, w_b, wall_b, _ = serve.serve_batched(trace, pool_bytes=pool, tick_iters=a.tick, max_iter=a.serve_max_iter)
+    print(f"# serving batched done: p50 {np.percentile(lat_b, 50):.3f} s", file=sys.stderr, flush=True)
+    lat_f, w_f, wall_f, _ = serve.serve_fifo(trace, max_iter=a.serve_max_iter)
+    print(f"# serving fifo done: p50 {np.percentile(lat_f, 50):.3f} s", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{a.serve_n} requests (seed 7), Poisson arrivals at 0.8 x measured batched capacity, "
+                    f"L in {{64, 256, 1024, 2048}} w.p. 0.4/0.3/0.2/0.1, f ~ U[0.05, 0.4], equibiaxial or shear "
+                    f"w.p. 1/2, 10-40 load steps, tol 1e-6, FP32, max_iter {a.serve_max_iter}, pool "
+                    f"{a.serve_pool_gb:g} GiB, {a.tick} iterations per tick",
+        "capacity_req_per_s": cap, "arrival_rate_req_per_s": rate,
+        "batched": dict(serve.percentiles(lat_b), pixel_iters_per_s=w_b / wall_b, wall_s=wall_b),
+        "fifo_one_at_a_time": dict(serve.percentiles(lat_f), pixel_iters_per_s=w_f / wall_f, wall_s=wall_f),
+    }
+
+
 def cpu_baseline(L):
     """The FP64 oracle on this host: one iteration of the first load step."""
     import numpy as np
@@ -121,14 +231,14 @@ def cpu_baseline(L):
     E = synth.load_path("shear", 40, 4.0)[0]
     s = alm.Solver(mask, alm.Params(L=L))
     s.start(E)
-    n = 1
+    n = 3
     t0 = time.perf_counter()
     for _ in range(n):
         s.iterate(E)
     dt = time.perf_counter() - t0
     del s
     return dict(value=L * L * n / dt, unit="pixel-iters/s", cores=1, host_cores=cores, kind="oracle",
-                sample=f"{n} augmented-Lagrangian iteration of load step 1 at L={L} (FP64 numpy, "
+                sample=f"{n} augmented-Lagrangian iterations of load step 1 at L={L} (FP64 numpy, "
                        f"numpy FFT single-threaded; Green tensor setup excluded), {dt:.1f} s")
 
 
@@ -157,6 +267,8 @@ def main():
     if not a.no_fp64:
         r64 = run_gpu(L, "fp64", min(a.steps, 2), 1, min(a.max_iter, 200))
         print(f"# fp64 done: {r64['value']:.4e} px-iter/s", file=sys.stderr, flush=True)
+    batched = None if a.no_batch else batched_section(a)
+    serving = None if a.no_serve else serving_section(a)
     cpu = None if a.no_cpu else cpu_baseline(L)
     ms_per_step = 1e3 * r32["seconds"] / a.steps
     out = {
@@ -188,6 +300,8 @@ def main():
         "iterations": r32["info"],
         "fp64": None if r64 is None else {"value": r64["value"], "unit": "pixel-iters/s",
                                           "iters_per_step": r64["info"]["iters_per_step"]},
+        "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -105,3 +105,25 @@ def batch_realizations(n: int = 256, base_seed: int = 1000):
         kind = "equibiaxial" if r % 2 == 0 else "shear"
         out.append(dict(r=r, seed=seed, L=L, f=f, kind=kind, steps=20))
     return out
+
+
+def serving_trace(n: int = 200, seed: int = 7, rate: float = 1.0):
+    """Requests of the serving workload, in arrival order.
+
+    Poisson arrivals at `rate` requests per second (exponential gaps drawn
+    from the counter-based uniform), L from {64, 256, 1024, 2048} with
+    weights 0.4 / 0.3 / 0.2 / 0.1, f uniform in [0.05, 0.4], equibiaxial or
+    shear loading with probability 1/2 each, and 10 to 40 load steps.
+    """
+    out = []
+    t = 0.0
+    for i in range(n):
+        u = [float(uniform01(seed, np.uint64(8 * i + k))) for k in range(5)]
+        t += -np.log1p(-u[0]) / rate
+        L = 64 if u[1] < 0.4 else 256 if u[1] < 0.7 else 1024 if u[1] < 0.9 else 2048
+        f = 0.05 + 0.35 * u[2]
+        kind = "equibiaxial" if u[3] < 0.5 else "shear"
+        steps = 10 + min(int(u[4] * 31), 30)
+        out.append(dict(i=i, arrival=t, L=L, f=f, kind=kind, steps=steps, seed=seed * 100003 + i))
+    return out
+
