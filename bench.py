@@ -29,6 +29,38 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["pm_fft.hpp", "pm_kernels.hpp", "pm_internal.h", "pm_row_f32.hip", "pm_col_f32.hip"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_L4096_fp32_shear.md")
+
+
+def kernel_sources_digest() -> str:
+    """SHA-256 over the sources of the FP32 row and column kernels."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0802_2488_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of k_row / k_column from the committed counter
+    summary, if it was taken from the kernels as they are now; else None."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for ln in lines:
+        if ln.startswith("traffic:"):
+            for kv in ln.split()[1:]:
+                k, v = kv.split("=")
+                vals[k] = v
+    if vals.get("sources_sha256") != kernel_sources_digest():
+        return None
+    return {"k_row": float(vals["k_row_bytes"]), "k_column": float(vals["k_column_bytes"])}
 
 
 def parse():
@@ -271,6 +303,7 @@ def main():
     serving = None if a.no_serve else serving_section(a)
     cpu = None if a.no_cpu else cpu_baseline(L)
     ms_per_step = 1e3 * r32["seconds"] / a.steps
+    traffic = measured_traffic() if L == 4096 else None
     out = {
         "metric": "pixel-iters/s at L=4096 FP32 vs FP64; batched p50/p99 solve latency",
         "value": r32["value"],
@@ -291,10 +324,12 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_row (inverse row FFT + pointwise step + forward row FFT)",
                      "achieved": row_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": row_gbs / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": row_b, "avg_launch_ms": row_avg_ms},
+                     "traffic": None if traffic is None else traffic["k_row"],
+                     "algorithmic_bytes_per_launch": row_b, "avg_launch_ms": row_avg_ms},
         "kernels": {
             "k_column": {"achieved_GBs": col_gbs, "frac": col_gbs / HBM_PEAK_GBS, "avg_launch_ms": col_avg_ms,
-                         "algorithmic_bytes_per_launch": col_b},
+                         "algorithmic_bytes_per_launch": col_b,
+                         "traffic": None if traffic is None else traffic["k_column"]},
             "reductions_ms_per_iter": tm["other_ms"] / max(tm["iterations"], 1),
         },
         "iterations": r32["info"],
