@@ -23,6 +23,40 @@ struct alignas(2 * sizeof(T)) cx {
   T re, im;
 };
 
+// Pointer into global memory.  Buffers reached through a descriptor read
+// from memory are generic pointers to the compiler, and generic accesses
+// become flat instructions, which also count against the LDS wait counter;
+// kernels convert such pointers with glb() so their accesses are global.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+
+// Complex loads and stores through LDS (generic) or global pointers; the
+// global forms move both parts as one 2-vector.
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ cx<T> ldc(const cx<T>* p) { return *p; }
+template <typename T>
+__device__ __forceinline__ cx<T> ldc(gptr<const cx<T>> p) {
+  const vec2<T> v = *(gptr<const vec2<T>>)p;
+  return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> ldc(gptr<cx<T>> p) { return ldc((gptr<const cx<T>>)p); }
+template <typename T>
+__device__ __forceinline__ void stc(cx<T>* p, cx<T> a) { *p = a; }
+template <typename T>
+__device__ __forceinline__ void stc(gptr<cx<T>> p, cx<T> a) {
+  vec2<T> v;
+  v.x = a.re;
+  v.y = a.im;
+  *(gptr<vec2<T>>)p = v;
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename T>
@@ -173,8 +207,8 @@ struct LdsSize {
 
 // Twiddle exp(DIR * 2 pi i * idx / N) from a forward table tw[i] = exp(-2 pi i i / N).
 template <int DIR, typename T>
-__device__ __forceinline__ cx<T> twl(const cx<T>* __restrict__ tw, int idx) {
-  cx<T> w = tw[idx];
+__device__ __forceinline__ cx<T> twl(gptr<const cx<T>> __restrict__ tw, int idx) {
+  cx<T> w = ldc(tw + idx);
   if constexpr (DIR > 0) w.im = -w.im;
   return w;
 }
@@ -182,7 +216,7 @@ __device__ __forceinline__ cx<T> twl(const cx<T>* __restrict__ tw, int idx) {
 // Multiply u[1..R-1] by w^r, w = exp(DIR 2 pi i base / N); the powers 1, 2, 4, 8
 // come from the table, the others from at most three products.
 template <int DIR, int R, typename T>
-__device__ __forceinline__ void apply_tw(cx<T>* u, const cx<T>* __restrict__ tw, int base) {
+__device__ __forceinline__ void apply_tw(cx<T>* u, gptr<const cx<T>> __restrict__ tw, int base) {
   if constexpr (R == 2) {
     u[1] = cmul(u[1], twl<DIR>(tw, base));
   } else if constexpr (R == 4) {
@@ -215,7 +249,7 @@ __device__ __forceinline__ void apply_tw(cx<T>* u, const cx<T>* __restrict__ tw,
 // write LDS.  Barriers are placed so one LDS buffer can be reused.
 template <int DIR, typename T, int N, int RMAX, int STAGE>
 __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__ lre, T* __restrict__ lim,
-                                               int t, const cx<T>* __restrict__ tw) {
+                                               int t, gptr<const cx<T>> __restrict__ tw) {
   using P = Plan<N, RMAX>;
   constexpr int R = P::radix(STAGE);
   constexpr int NS = P::ns(STAGE);
@@ -269,7 +303,7 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__
 }
 
 template <int DIR, typename T, int N, int RMAX, int STAGE = 0>
-__device__ __forceinline__ void fft_stages(cx<T> (&v)[RMAX], T* lre, T* lim, int t, const cx<T>* tw) {
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[RMAX], T* lre, T* lim, int t, gptr<const cx<T>> tw) {
   stockham_stage<DIR, T, N, RMAX, STAGE>(v, lre, lim, t, tw);
   if constexpr (STAGE + 1 < Plan<N, RMAX>::NSTAGE) fft_stages<DIR, T, N, RMAX, STAGE + 1>(v, lre, lim, t, tw);
 }
@@ -277,11 +311,11 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[RMAX], T* lre, T* lim, int
 // Length-N transform of one signal held in pattern A by a team of Plan::TPF
 // threads; every thread of the block must call it (it contains barriers).
 template <int DIR, typename T, int N, int RMAX>
-__device__ __forceinline__ void fft(cx<T> (&v)[RMAX], T* lre, T* lim, int t, const cx<T>* tw) {
+__device__ __forceinline__ void fft(cx<T> (&v)[RMAX], T* lre, T* lim, int t, gptr<const cx<T>> tw) {
   // An opaque copy of the table pointer behind a compiler memory barrier:
   // twiddle loads cannot be hoisted out of the transform and held live
   // across unrelated work.
-  const cx<T>* twp = tw;
+  gptr<const cx<T>> twp = tw;
   asm volatile("" : "+s"(twp) : : "memory");
   fft_stages<DIR, T, N, RMAX, 0>(v, lre, lim, t, twp);
 }

@@ -89,7 +89,8 @@ struct Extra {
 };
 
 template <typename T>
-__device__ __forceinline__ bool gated_out(const Extra<T>& x, const DevState* st) {
+__device__ __forceinline__ bool gated_out(const Extra<T>& x, const DevState* st_generic) {
+  gptr<const DevState> st = glb(st_generic);
   return (x.gate == GATE_RUNNING && st->halted) || (x.gate == GATE_PENDING && !st->pending);
 }
 

@@ -11,9 +11,10 @@
 //   reductions  : fixed-order FP64 sums, convergence indicators, and the
 //                 backward-difference equilibrium residual when the other two
 //                 indicators already pass                      (k_reduce*, k_div)
-// The persistent state is the strain eps (4 planes: 11, 22, 33, 12) and the
-// half spectrum; the Lagrange multiplier equals S(eps) after every iteration
-// and is recomputed instead of stored.
+// The persistent state is the stress of the last iterate (4 planes: 11, 22,
+// 33, 12), which is also the augmented-Lagrangian multiplier, and the half
+// spectrum of the polarisation tau; the strain is recovered from both when
+// outputs are written.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,7 +26,7 @@
 
 // Tuning knobs (compile-time; the defaults are the measured best on MI355X).
 #ifndef PM_ROW_R32
-#define PM_ROW_R32 8          // row-pass radix, FP32
+#define PM_ROW_R32 16         // row-pass radix, FP32
 #endif
 #ifndef PM_ROW_R64
 #define PM_ROW_R64 4          // row-pass radix, FP64
@@ -47,6 +48,9 @@
 #endif
 #ifndef PM_COL_W32
 #define PM_COL_W32 2          // columns per block (= spectrum tile width), FP32, long columns
+#endif
+#ifndef PM_COL_CB32
+#define PM_COL_CB32 2         // columns per block, FP32, columns of 256 threads
 #endif
 #ifndef PM_COL_WPE
 #define PM_COL_WPE 2
@@ -169,8 +173,8 @@ __device__ __forceinline__ void strain_from(const T* sg, const T* tau, bool is_v
 
 // ---------------------------------------------------------------------------
 // Block reduction of NV doubles in a fixed order (wave shuffles, then LDS).
-template <int NV>
-__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __restrict__ out) {
+template <int NV, typename P>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], P out) {
   __shared__ double red[16][NV];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -219,14 +223,20 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-// Whether a row pair's spectrum slice is staged through LDS: FFT buffers,
-// the stage (3 L complex per team), the per-thread sums and the reduction
-// scratch must fit in the 160 KiB of LDS of a CU.
+// LDS of one row-pass block.  One region serves in turn as the stage of one
+// row of each team's pair (HBM <-> LDS copies in 16-byte units), as the FFT
+// exchange buffers and as the per-thread sums of the pointwise step; the
+// phases are separated by block barriers.  Rows are staged when the region
+// still leaves room for two blocks per CU.
 template <typename T, int L, int TEAMS, int TPF>
-struct RowStage {
-  static constexpr size_t bytes = (size_t)TEAMS * 2 * LdsSize<L>::value * sizeof(T) +
-                                  (size_t)TEAMS * 3 * L * 2 * sizeof(T) + NSUM * (size_t)TEAMS * TPF * sizeof(T) + 16 * 5 * 8;
-  static constexpr bool value = bytes <= 150 * 1024;
+struct RowLds {
+  static constexpr size_t stage = (size_t)TEAMS * (L / 2) * 3 * sizeof(cx<T>);
+  static constexpr size_t fftb = (size_t)TEAMS * 2 * LdsSize<L>::value * sizeof(T);
+  static constexpr size_t sums = (size_t)NSUM * TEAMS * TPF * sizeof(T);
+  static constexpr size_t base = fftb > sums ? fftb : sums;
+  static constexpr size_t with_stage = stage > base ? stage : base;
+  static constexpr bool staged = with_stage <= 78 * 1024;
+  static constexpr size_t bytes = staged ? with_stage : base;
 };
 
 // A row pair's view of the half spectrum: bins m1 of rows (ra + r), r = 0, 1,
@@ -239,12 +249,12 @@ __device__ __forceinline__ unsigned pidx(int m1, int r, int c) {
 }
 
 // Row-pass output: split the complex transform Z of x + i y into the half
-// spectra X (component cxi of row rx) and Y (component cyi of row ry);
-// X[m] = (Z[m] + conj Z[L-m]) / 2, Y[m] = (Z[m] - conj Z[L-m]) / (2i), with
-// the real Nyquist values packed into the imaginary slots of bin 0.
-template <typename T, int L, int RMAX, int WT, int TSTRIDE>
-__device__ __forceinline__ void split_store(const cx<T> (&z)[RMAX], T* lre, T* lim, int t, cx<T>* __restrict__ base,
-                                            int rx, int cxi, int ry, int cyi) {
+// spectra X[m] = (Z[m] + conj Z[L-m]) / 2 and Y[m] = (Z[m] - conj Z[L-m]) / (2i),
+// m < L/2, with the real Nyquist values packed into the imaginary slots of
+// bin 0.  Thread t gets bins m = t + TPF k, k < RMAX / 2.
+template <typename T, int L, int RMAX>
+__device__ __forceinline__ void split_regs(const cx<T> (&z)[RMAX], T* lre, T* lim, int t, cx<T> (&X)[RMAX / 2],
+                                           cx<T> (&Y)[RMAX / 2]) {
   constexpr int TPF = L / RMAX;
   __syncthreads();
 #pragma unroll
@@ -261,43 +271,56 @@ __device__ __forceinline__ void split_store(const cx<T> (&z)[RMAX], T* lre, T* l
     const cx<T> zm = {lre[i0], lim[i0]};
     const cx<T> zr = {lre[i1], -lim[i1]};   // conj Z[L - m]
     const cx<T> d = zm - zr;
-    cx<T> X = cscale(zm + zr, (T)0.5);
-    cx<T> Y = {d.im * (T)0.5, -d.re * (T)0.5};
+    X[k] = cscale(zm + zr, (T)0.5);
+    Y[k] = {d.im * (T)0.5, -d.re * (T)0.5};
     if (mm == 0) {
       const int ih = lpad(L / 2);
-      X.im = lre[ih];   // Re Z[L/2]: Nyquist bin of x
-      Y.im = lim[ih];   // Im Z[L/2]: Nyquist bin of y
+      X[k].im = lre[ih];   // Re Z[L/2]: Nyquist bin of x
+      Y[k].im = lim[ih];   // Im Z[L/2]: Nyquist bin of y
     }
-    base[pidx<WT, TSTRIDE>(mm, rx, cxi)] = X;
-    base[pidx<WT, TSTRIDE>(mm, ry, cyi)] = Y;
+  }
+}
+
+// Components 0, 1, 2 of row r of the pair at bins t + TPF k, k < H.
+template <typename T, int L, int H, int WT, int TSTRIDE, typename P>
+__device__ __forceinline__ void put_row(P base, int t, int r, const cx<T> (&c0)[H],
+                                        const cx<T> (&c1)[H], const cx<T> (&c2)[H]) {
+  constexpr int TPF = L / (2 * H);
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const int mm = t + TPF * k;
+    stc(base + pidx<WT, TSTRIDE>(mm, r, 0), c0[k]);
+    stc(base + pidx<WT, TSTRIDE>(mm, r, 1), c1[k]);
+    stc(base + pidx<WT, TSTRIDE>(mm, r, 2), c2[k]);
   }
 }
 
 // Hermitian extension of a packed row spectrum at bin m in [0, L).
-template <typename T, int L, int WT, int TSTRIDE>
-__device__ __forceinline__ cx<T> load_bin(const cx<T>* __restrict__ base, int m, int r, int c) {
-  if (m == 0) return {base[pidx<WT, TSTRIDE>(0, r, c)].re, (T)0};
-  if (m == L / 2) return {base[pidx<WT, TSTRIDE>(0, r, c)].im, (T)0};
-  if (m < L / 2) return base[pidx<WT, TSTRIDE>(m, r, c)];
-  return cconj(base[pidx<WT, TSTRIDE>(L - m, r, c)]);
+template <typename T, int L, int WT, int TSTRIDE, typename P>
+__device__ __forceinline__ cx<T> load_bin(P base, int m, int r, int c) {
+  if (m == 0) return {ldc(base + pidx<WT, TSTRIDE>(0, r, c)).re, (T)0};
+  if (m == L / 2) return {ldc(base + pidx<WT, TSTRIDE>(0, r, c)).im, (T)0};
+  if (m < L / 2) return ldc(base + pidx<WT, TSTRIDE>(m, r, c));
+  return cconj(ldc(base + pidx<WT, TSTRIDE>(L - m, r, c)));
 }
 
-// Copy a row pair's slice of the half spectrum between HBM and its LDS
-// stage in 16-byte units: tile j holds 2 WT 3 contiguous complex values of
-// rows ra, ra + 1 (ra even), so each lane moves 16 contiguous bytes.
+// Copy row r (0 or 1) of a row pair's slice of the half spectrum between HBM
+// and its LDS stage in 16-byte units: in tile j the row holds WT 3
+// contiguous complex values, and the stage keeps them in tile order.
 template <typename T, int L, int WT, int TPF, bool TO_LDS>
-__device__ __forceinline__ void stage_copy(cx<T>* __restrict__ g, cx<T>* __restrict__ st, int t) {
-  constexpr int CPT = 2 * WT * 3;                       // complex values per tile and row pair
-  constexpr int UPT = CPT * (int)sizeof(cx<T>) / 16;    // 16-byte units per tile
+__device__ __forceinline__ void stage_row(gptr<cx<T>> __restrict__ g, cx<T>* __restrict__ st, int t, int r) {
+  constexpr int CPT = WT * 3;                           // complex values per tile and row
+  constexpr int UPT = CPT * (int)sizeof(cx<T>) / 16;    // 16-byte units per tile and row
   constexpr int NU = (L / 2 / WT) * UPT;
-  static_assert((CPT * sizeof(cx<T>)) % 16 == 0, "tile slice must be a whole number of 16-byte units");
-  const uint4* __restrict__ gs = reinterpret_cast<const uint4*>(g);
-  uint4* __restrict__ gd = reinterpret_cast<uint4*>(g);
-  uint4* __restrict__ ls = reinterpret_cast<uint4*>(st);
+  static_assert((CPT * sizeof(cx<T>)) % 16 == 0, "a tile row must be a whole number of 16-byte units");
+  using u4 = unsigned __attribute__((ext_vector_type(4)));
+  gptr<const u4> __restrict__ gs = (gptr<const u4>)g;
+  gptr<u4> __restrict__ gd = (gptr<u4>)g;
+  u4* __restrict__ ls = reinterpret_cast<u4*>(st);
 #pragma unroll 4
   for (int u = t; u < NU; u += TPF) {
     const int j = u / UPT, k = u - j * UPT;
-    const unsigned gi = (unsigned)j * (L * WT * 3 * (int)sizeof(cx<T>) / 16) + k;
+    const unsigned gi = (unsigned)j * (L * WT * 3 * (int)sizeof(cx<T>) / 16) + r * UPT + k;
     if constexpr (TO_LDS) ls[u] = gs[gi];
     else gd[gi] = ls[u];
   }
@@ -322,23 +345,24 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   constexpr int LOAD_GROUP = RMAX >= 4 ? 4 : RMAX;   // unrolled iterations whose loads may be in flight together
   constexpr bool LOADS_SPEC = MODE == ROW_ITER || MODE == ROW_INV || MODE == ROW_EMIT;
   constexpr bool POINTWISE = MODE == ROW_ITER || MODE == ROW_INIT;
-  constexpr bool STAGED = RowStage<T, L, TEAMS, TPF>::value;
-  constexpr int GSTRIDE = L * WT * 3, SSTRIDE = 2 * WT * 3;
+  constexpr bool STAGED = RowLds<T, L, TEAMS, TPF>::staged;
+  constexpr int GSTRIDE = L * WT * 3, SSTRIDE = WT * 3;
   constexpr int BPS = (L / 2) / TEAMS;                 // blocks per slot
   const Slot<T>& S = slots[blockIdx.x / BPS];
   if (gated_out(x, S.st)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int team = threadIdx.x / TPF;
   const int t = threadIdx.x % TPF;
+  // one LDS region, used in turn as row stage, FFT buffers and sums
   T* lre = reinterpret_cast<T*>(smem_raw) + team * 2 * LS;
   T* lim = lre + LS;
-  // LDS stage of this team's row pair: 3 L complex values after the FFT buffers
-  cx<T>* stg = reinterpret_cast<cx<T>*>(reinterpret_cast<T*>(smem_raw) + TEAMS * 2 * LS) + team * 3 * L;
+  cx<T>* stg = reinterpret_cast<cx<T>*>(smem_raw) + team * (L / 2) * 3;
   const int p = xcd_remap(blockIdx.x % BPS, BPS) * TEAMS + team;
   const int ra = 2 * p, rb = 2 * p + 1;
-  cx<T>* __restrict__ spec = S.spec;
-  cx<T>* __restrict__ gbase = spec + (size_t)ra * WT * 3;
-  const cx<T>* __restrict__ tw = S.tw;
+  gptr<cx<T>> __restrict__ gbase = glb(S.spec) + (size_t)ra * WT * 3;
+  gptr<const cx<T>> __restrict__ tw = glb(S.tw);
+  gptr<const uint8_t> __restrict__ mask = glb(S.mask);
+  gptr<T> __restrict__ sig = glb(S.sig);
   const Mat<T> m = make_mat<T>(S.prm);
   constexpr unsigned NPX = (unsigned)L * L;
 
@@ -354,10 +378,10 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const unsigned ix = (unsigned)(half ? rb : ra) * L + t + TPF * s;
-      mk[s][half] = S.mask[ix];
+      mk[s][half] = mask[ix];
       if constexpr (MODE == ROW_ITER) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) so[s][half][c] = S.sig[c * NPX + ix];
+        for (int c = 0; c < 4; ++c) so[s][half][c] = sig[c * NPX + ix];
       }
     }
   };
@@ -367,7 +391,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   }
 
   if constexpr (LOADS_SPEC) {
-    auto build = [&](const cx<T>* base, auto tstride) {
+    auto build = [&](auto base, auto tstride) {
       constexpr int TS = decltype(tstride)::value;
 #pragma unroll
       for (int s = 0; s < RMAX; ++s) {
@@ -383,9 +407,28 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       }
     };
     if constexpr (STAGED) {
-      stage_copy<T, L, WT, TPF, true>(gbase, stg, t);
+      // row a: Za = 11a + i 22a and the 12a part of Zc
+      stage_row<T, L, WT, TPF, true>(gbase, stg, t, 0);
       __syncthreads();
-      build(stg, std::integral_constant<int, SSTRIDE>{});
+#pragma unroll
+      for (int s = 0; s < RMAX; ++s) {
+        const int mm = t + TPF * s;
+        const cx<T> a0 = load_bin<T, L, WT, SSTRIDE>(stg, mm, 0, 0), a1 = load_bin<T, L, WT, SSTRIDE>(stg, mm, 0, 1);
+        za[s] = {a0.re - a1.im, a0.im + a1.re};
+        zc[s] = load_bin<T, L, WT, SSTRIDE>(stg, mm, 0, 2);
+      }
+      __syncthreads();
+      // row b: Zb = 11b + i 22b, and Zc = 12a + i 12b
+      stage_row<T, L, WT, TPF, true>(gbase, stg, t, 1);
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < RMAX; ++s) {
+        const int mm = t + TPF * s;
+        const cx<T> b0 = load_bin<T, L, WT, SSTRIDE>(stg, mm, 0, 0), b1 = load_bin<T, L, WT, SSTRIDE>(stg, mm, 0, 1);
+        const cx<T> b2 = load_bin<T, L, WT, SSTRIDE>(stg, mm, 0, 2);
+        zb[s] = {b0.re - b1.im, b0.im + b1.re};
+        zc[s] = {zc[s].re - b2.im, zc[s].im + b2.re};
+      }
     } else {
       build(gbase, std::integral_constant<int, GSTRIDE>{});
     }
@@ -397,12 +440,13 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   }
 
   if constexpr (MODE == ROW_INV) {
+    gptr<T> __restrict__ out = glb(x.real_out);
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
       const int x1 = t + TPF * s;
       const unsigned ia = (unsigned)ra * L + x1, ib = (unsigned)rb * L + x1;
-      x.real_out[ia] = za[s].re; x.real_out[NPX + ia] = za[s].im; x.real_out[2 * NPX + ia] = zc[s].re;
-      x.real_out[ib] = zb[s].re; x.real_out[NPX + ib] = zb[s].im; x.real_out[2 * NPX + ib] = zc[s].im;
+      out[ia] = za[s].re; out[NPX + ia] = za[s].im; out[2 * NPX + ia] = zc[s].re;
+      out[ib] = zb[s].re; out[NPX + ib] = zb[s].im; out[2 * NPX + ib] = zc[s].im;
     }
     return;
   }
@@ -410,6 +454,9 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   if constexpr (MODE == ROW_EMIT) {
     // the stored row spectra hold the forward row transforms of tau
     const T invL = (T)(1.0 / L);
+    gptr<T> __restrict__ sig_out = glb(x.sig_out);
+    gptr<T> __restrict__ eps_out = glb(x.eps_out);
+    gptr<uint8_t> __restrict__ pl_out = glb(x.plastic_out);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
@@ -417,40 +464,41 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
-        const bool isv = S.mask[ix] != 0;
+        const bool isv = mask[ix] != 0;
         T tau[3];
         if (half == 0) { tau[0] = za[s].re * invL; tau[1] = za[s].im * invL; tau[2] = zc[s].re * invL; }
         else { tau[0] = zb[s].re * invL; tau[1] = zb[s].im * invL; tau[2] = zc[s].im * invL; }
-        T sg[4] = {S.sig[ix], S.sig[NPX + ix], S.sig[2 * NPX + ix], S.sig[3 * NPX + ix]};
+        T sg[4] = {sig[ix], sig[NPX + ix], sig[2 * NPX + ix], sig[3 * NPX + ix]};
         T en[4];
         strain_from(sg, tau, isv, m, en);
         T dummy[4];
         const bool pl = !isv && hencky(en, dummy, m);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] += (double)en[c];
-        if (x.sig_out) {
+        if (sig_out) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) x.sig_out[c * NPX + ix] = sg[c];
+          for (int c = 0; c < 4; ++c) sig_out[c * NPX + ix] = sg[c];
         }
-        if (x.eps_out) {
+        if (eps_out) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) x.eps_out[c * NPX + ix] = en[c];
+          for (int c = 0; c < 4; ++c) eps_out[c * NPX + ix] = en[c];
         }
-        if (x.plastic_out) x.plastic_out[ix] = pl ? 1 : 0;
+        if (pl_out) pl_out[ix] = pl ? 1 : 0;
       }
     }
-    block_reduce_store<4>(acc, S.part2 + (size_t)(blockIdx.x % BPS) * 4);
+    block_reduce_store<4>(acc, glb(S.part2) + (size_t)(blockIdx.x % BPS) * 4);
     return;
   }
 
   if constexpr (MODE == ROW_FWD) {
+    gptr<const T> __restrict__ in = glb(x.real_in);
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
       const int x1 = t + TPF * s;
       const unsigned ia = (unsigned)ra * L + x1, ib = (unsigned)rb * L + x1;
-      za[s] = {x.real_in[ia], x.real_in[NPX + ia]};
-      zb[s] = {x.real_in[ib], x.real_in[NPX + ib]};
-      zc[s] = {x.real_in[2 * NPX + ia], x.real_in[2 * NPX + ib]};
+      za[s] = {in[ia], in[NPX + ia]};
+      zb[s] = {in[ib], in[NPX + ib]};
+      zc[s] = {in[2 * NPX + ia], in[2 * NPX + ib]};
     }
   }
 
@@ -459,11 +507,14 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
     // (sigma 11, 22, 33, 12 and |e - eps|^2) are kept in LDS rather than
     // registers, which keeps the kernel free of spills; block and global
     // sums are FP64.
-    __shared__ T lacc[NSUM][BS];
-    T* __restrict__ sig = S.sig;
+    T(*lacc)[BS] = reinterpret_cast<T(*)[BS]>(smem_raw);
+    __syncthreads();   // the region may still be read by the last FFT stage or the row build
     // ROW_INIT: the load step's E from the slot state, or from the arguments
-    const double* Ed = x.use_state ? S.st->E : x.E;
-    const T E0 = (T)Ed[0], E1 = (T)Ed[1], E2 = (T)Ed[2];
+    T E0 = (T)x.E[0], E1 = (T)x.E[1], E2 = (T)x.E[2];
+    if (x.use_state) {
+      gptr<const DevState> st = glb(S.st);
+      E0 = (T)st->E[0]; E1 = (T)st->E[1]; E2 = (T)st->E[2];
+    }
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) lacc[i][threadIdx.x] = (T)0;
 #pragma unroll
@@ -510,7 +561,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
     double accd[NSUM];
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) accd[i] = (double)lacc[i][threadIdx.x];
-    block_reduce_store<NSUM>(accd, S.part + (size_t)(blockIdx.x % BPS) * NPART);
+    block_reduce_store<NSUM>(accd, glb(S.part) + (size_t)(blockIdx.x % BPS) * NPART);
   }
 
   fft<-1, T, L, RMAX>(za, lre, lim, t, tw);
@@ -518,16 +569,23 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   fft<-1, T, L, RMAX>(zc, lre, lim, t, tw);
 
   // Za -> (11, 22) of row a, Zb -> (11, 22) of row b, Zc -> 12 of rows a, b.
+  constexpr int H = RMAX / 2;
+  cx<T> xa[H], ya[H], xb[H], yb[H], xc[H], yc[H];
+  split_regs<T, L, RMAX>(za, lre, lim, t, xa, ya);
+  split_regs<T, L, RMAX>(zb, lre, lim, t, xb, yb);
+  split_regs<T, L, RMAX>(zc, lre, lim, t, xc, yc);
   if constexpr (STAGED) {
-    split_store<T, L, RMAX, WT, SSTRIDE>(za, lre, lim, t, stg, 0, 0, 0, 1);
-    split_store<T, L, RMAX, WT, SSTRIDE>(zb, lre, lim, t, stg, 1, 0, 1, 1);
-    split_store<T, L, RMAX, WT, SSTRIDE>(zc, lre, lim, t, stg, 0, 2, 1, 2);
     __syncthreads();
-    stage_copy<T, L, WT, TPF, false>(gbase, stg, t);
+    put_row<T, L, H, WT, SSTRIDE>(stg, t, 0, xa, ya, xc);
+    __syncthreads();
+    stage_row<T, L, WT, TPF, false>(gbase, stg, t, 0);
+    __syncthreads();
+    put_row<T, L, H, WT, SSTRIDE>(stg, t, 0, xb, yb, yc);
+    __syncthreads();
+    stage_row<T, L, WT, TPF, false>(gbase, stg, t, 1);
   } else {
-    split_store<T, L, RMAX, WT, GSTRIDE>(za, lre, lim, t, gbase, 0, 0, 0, 1);
-    split_store<T, L, RMAX, WT, GSTRIDE>(zb, lre, lim, t, gbase, 1, 0, 1, 1);
-    split_store<T, L, RMAX, WT, GSTRIDE>(zc, lre, lim, t, gbase, 0, 2, 1, 2);
+    put_row<T, L, H, WT, GSTRIDE>(gbase, t, 0, xa, ya, xc);
+    put_row<T, L, H, WT, GSTRIDE>(gbase, t, 1, xb, yb, yc);
   }
 }
 
@@ -568,50 +626,57 @@ __device__ __forceinline__ void green_at(cx<T>* tt, int m1, int m2, const Slot<T
                                          const T lam0, const T mu0, const T scale) {
   if (m1 == 0 && m2 == 0) {
     double E0 = x.E[0], E1 = x.E[1], E2 = x.E[2];
-    if (x.use_state) { E0 = S.st->E[0]; E1 = S.st->E[1]; E2 = S.st->E[2]; }
+    if (x.use_state) {
+      gptr<const DevState> st = glb(S.st);
+      E0 = st->E[0]; E1 = st->E[1]; E2 = st->E[2];
+    }
     tt[0] = {(T)E0, (T)0};
     tt[1] = {(T)E1, (T)0};
     tt[2] = {(T)E2, (T)0};
     return;
   }
-  cx<T> k1 = S.ktab[m1], k2 = S.ktab[m2];
+  gptr<const cx<T>> ktab = glb(S.ktab);
+  cx<T> k1 = ldc(ktab + m1), k2 = ldc(ktab + m2);
   if (S.flip1) k1 = {-k1.re, k1.im};   // k(-q) = -conj(k(q))
   if (S.flip2) k2 = {-k2.re, k2.im};
   green_apply(tt, k1, k2, lam0, mu0, scale);
 }
 
 // A team of TPF threads owns one column m1 of the packed row spectra; a
-// block owns one tile of W adjacent columns (contiguous in memory), with the
-// column index fastest across lanes.  Column 0 carries the real bins
-// m1 = 0 (real part) and m1 = L/2 (imaginary part): its transform is split
-// with conj-symmetry into the two real-signal spectra, each gets its own
-// Green tensor, and the results are packed again before the inverse.
-template <typename T, int L, int RMAX, int W, int MODE>
-__global__ void __launch_bounds__(W*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_COL_WPE)))
+// block owns CB adjacent columns, with the column index fastest across
+// lanes.  Columns are stored in tiles of W (contiguous in memory); CB divides
+// W, or equals it.  Column 0 carries the real bins m1 = 0 (real part) and
+// m1 = L/2 (imaginary part): its transform is split with conj-symmetry into
+// the two real-signal spectra, each gets its own Green tensor, and the
+// results are packed again before the inverse.
+template <typename T, int L, int RMAX, int W, int CB, int MODE>
+__global__ void __launch_bounds__(CB*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_COL_WPE)))
 k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
+  static_assert(W % CB == 0, "columns per block must divide the tile width");
   constexpr int TPF = L / RMAX;
   constexpr int LS = LdsSize<L>::value;
-  constexpr int BPS = (L / 2) / W;                     // blocks (tiles) per slot
+  constexpr int BPS = (L / 2) / CB;                    // blocks per slot
   const Slot<T>& S = slots[blockIdx.x / BPS];
   if (gated_out(x, S.st)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int w = threadIdx.x % W;
-  const int t = threadIdx.x / W;
-  T* lre = reinterpret_cast<T*>(smem_raw) + w * 2 * LS;
+  const int wb = threadIdx.x % CB;        // column within the block
+  const int t = threadIdx.x / CB;
+  T* lre = reinterpret_cast<T*>(smem_raw) + wb * 2 * LS;
   T* lim = lre + LS;
   const int g = xcd_remap(blockIdx.x % BPS, BPS);
-  const int m1 = g * W + w;
-  const bool packed = (g == 0);           // block-uniform: tile 0 holds column 0
-  cx<T>* __restrict__ spec = S.spec;
-  const cx<T>* __restrict__ tw = S.tw;
-  cx<T>* __restrict__ tile = spec + (size_t)g * L * W * 3;
+  const int m1 = g * CB + wb;
+  const int w = m1 % W;                   // column within its tile
+  const bool packed = (g == 0);           // block-uniform: block 0 holds column 0
+  gptr<const cx<T>> __restrict__ tw = glb(S.tw);
+  gptr<cx<T>> __restrict__ tile = glb(S.spec) + (size_t)(m1 / W) * L * W * 3;
+  gptr<cx<T>> __restrict__ xbuf = glb(S.xbuf);
 
   cx<T> v[3][RMAX];
 #pragma unroll
   for (int s = 0; s < RMAX; ++s) {
     const int m2 = t + TPF * s;
-    const cx<T>* q = tile + ((unsigned)m2 * W + w) * 3u;
-    v[0][s] = q[0]; v[1][s] = q[1]; v[2][s] = q[2];
+    gptr<const cx<T>> q = tile + ((unsigned)m2 * W + w) * 3u;
+    v[0][s] = ldc(q); v[1][s] = ldc(q + 1); v[2][s] = ldc(q + 2);
   }
   if constexpr ((MODE & COL_FWD) != 0) {
 #pragma unroll
@@ -624,15 +689,15 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
       // small global buffer to read the partners conj Z[L - m2]; the branch is
       // uniform over the block, and the barrier orders the global writes
       // before the reads within the block.
-      if (w == 0) {
+      if (wb == 0) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int s = 0; s < RMAX; ++s) S.xbuf[c * L + t + TPF * s] = v[c][s];
+          for (int s = 0; s < RMAX; ++s) stc(xbuf + (c * L + t + TPF * s), v[c][s]);
       }
       __threadfence_block();
       __syncthreads();
-      if (w == 0) {
+      if (wb == 0) {
 #pragma unroll
         for (int s = 0; s < RMAX; ++s) {
           const int m2 = t + TPF * s;
@@ -640,7 +705,7 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
           cx<T> x0[3], xn[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const cx<T> zr = cconj(S.xbuf[c * L + mr]);
+            const cx<T> zr = cconj(ldc(xbuf + (c * L + mr)));
             const cx<T> d = v[c][s] - zr;
             x0[c] = cscale(v[c][s] + zr, (T)0.5);
             xn[c] = {d.im * (T)0.5, -d.re * (T)0.5};
@@ -652,7 +717,7 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
         }
       }
     }
-    if (!packed || w != 0) {
+    if (!packed || wb != 0) {
 #pragma unroll
       for (int s = 0; s < RMAX; ++s) {
         const int m2 = t + TPF * s;
@@ -669,8 +734,8 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
 #pragma unroll
   for (int s = 0; s < RMAX; ++s) {
     const int m2 = t + TPF * s;
-    cx<T>* q = tile + ((unsigned)m2 * W + w) * 3u;
-    q[0] = v[0][s]; q[1] = v[1][s]; q[2] = v[2][s];
+    gptr<cx<T>> q = tile + ((unsigned)m2 * W + w) * 3u;
+    stc(q, v[0][s]); stc(q + 1, v[1][s]); stc(q + 2, v[2][s]);
   }
 }
 
@@ -694,17 +759,20 @@ struct Cfg {
   static constexpr int COL_W_RAW = COL_TPF >= 256 ? (sizeof(T) == 8 ? 1 : PM_COL_W32) : (256 / COL_TPF > 16 ? 16 : 256 / COL_TPF);
   static constexpr int COL_W_CAP = COL_W_RAW * COL_TPF > 1024 ? (1024 / COL_TPF > 0 ? 1024 / COL_TPF : 1) : COL_W_RAW;
   static constexpr int COL_W = COL_W_CAP > L / 2 ? L / 2 : COL_W_CAP;
+  // columns per block: the tile width, except FP32 columns of 512 threads,
+  // which run one per block
+  static constexpr int COL_CB =
+      (sizeof(T) == 4 && COL_TPF >= 256) ? (COL_TPF >= 512 ? 1 : (PM_COL_CB32 < COL_W ? PM_COL_CB32 : COL_W)) : COL_W;
 };
 
 template <typename T, int L>
 static size_t row_lds() {
   using C = Cfg<T, L>;
-  return (size_t)C::ROW_TEAMS * 2 * LdsSize<L>::value * sizeof(T) +
-         (RowStage<T, L, C::ROW_TEAMS, C::TPF>::value ? (size_t)C::ROW_TEAMS * 3 * L * sizeof(cx<T>) : 0);
+  return RowLds<T, L, C::ROW_TEAMS, C::TPF>::bytes;
 }
 template <typename T, int L>
 static size_t col_lds() {
-  return (size_t)Cfg<T, L>::COL_W * 2 * LdsSize<L>::value * sizeof(T);
+  return (size_t)Cfg<T, L>::COL_CB * 2 * LdsSize<L>::value * sizeof(T);
 }
 
 template <typename T, int L, int MODE>
@@ -726,7 +794,7 @@ static hipError_t launch_row_LM(const Slot<T>* slots, int nslots, const Extra<T>
 template <typename T, int L, int MODE>
 static hipError_t launch_col_LM(const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
   using C = Cfg<T, L>;
-  auto kern = k_column<T, L, C::COL_RMAX, C::COL_W, MODE>;
+  auto kern = k_column<T, L, C::COL_RMAX, C::COL_W, C::COL_CB, MODE>;
   static bool attr = false;
   const size_t lds = col_lds<T, L>();
   if (!attr) {
@@ -734,8 +802,8 @@ static hipError_t launch_col_LM(const Slot<T>* slots, int nslots, const Extra<T>
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const int grid = nslots * ((L / 2) / C::COL_W);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::COL_W * C::COL_TPF), lds, st, slots, x);
+  const int grid = nslots * ((L / 2) / C::COL_CB);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::COL_CB * C::COL_TPF), lds, st, slots, x);
   return hipGetLastError();
 }
 
