@@ -213,29 +213,60 @@ __device__ __forceinline__ cx<T> twl(gptr<const cx<T>> __restrict__ tw, int idx)
   return w;
 }
 
-// Multiply u[1..R-1] by w^r, w = exp(DIR 2 pi i base / N); the powers 1, 2, 4, 8
-// come from the table, the others from at most three products.
-template <int DIR, int R, typename T>
-__device__ __forceinline__ void apply_tw(cx<T>* u, gptr<const cx<T>> __restrict__ tw, int base) {
+// Twiddle seeds of one stage for one thread: for each of its B butterflies
+// the powers w, w^2, w^4, w^8 (as far as the radix needs) of
+// w = exp(DIR 2 pi i base / N), read from the table.  A stage's seeds are
+// loaded while the previous stage computes, so the table reads overlap work.
+template <typename T, int B>
+struct Seeds {
+  cx<T> w[B][4];
+};
+
+template <int DIR, typename T, int N, int RMAX, int STAGE>
+using StageSeeds = Seeds<T, RMAX / Plan<N, RMAX>::radix(STAGE)>;
+
+template <int DIR, typename T, int N, int RMAX, int STAGE>
+__device__ __forceinline__ void load_seeds(StageSeeds<DIR, T, N, RMAX, STAGE>& sd, gptr<const cx<T>> __restrict__ tw,
+                                           int t) {
+  using P = Plan<N, RMAX>;
+  constexpr int R = P::radix(STAGE);
+  constexpr int NS = P::ns(STAGE);
+  constexpr int B = RMAX / R;
+  if constexpr (NS > 1) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + b * P::TPF;
+      const int base = (j % NS) * (N / (NS * R));
+      sd.w[b][0] = twl<DIR>(tw, base);
+      if constexpr (R >= 4) sd.w[b][1] = twl<DIR>(tw, 2 * base);
+      if constexpr (R >= 8) sd.w[b][2] = twl<DIR>(tw, 4 * base);
+      if constexpr (R >= 16) sd.w[b][3] = twl<DIR>(tw, 8 * base);
+    }
+  }
+}
+
+// Multiply u[1..R-1] by w^r from the seeds w, w^2, w^4, w^8; the other
+// powers take at most three products.
+template <int R, typename T>
+__device__ __forceinline__ void apply_seeds(cx<T>* u, const cx<T> (&sd)[4]) {
   if constexpr (R == 2) {
-    u[1] = cmul(u[1], twl<DIR>(tw, base));
+    u[1] = cmul(u[1], sd[0]);
   } else if constexpr (R == 4) {
-    cx<T> w1 = twl<DIR>(tw, base), w2 = twl<DIR>(tw, 2 * base);
-    cx<T> w3 = cmul(w1, w2);
-    u[1] = cmul(u[1], w1);
-    u[2] = cmul(u[2], w2);
+    const cx<T> w3 = cmul(sd[0], sd[1]);
+    u[1] = cmul(u[1], sd[0]);
+    u[2] = cmul(u[2], sd[1]);
     u[3] = cmul(u[3], w3);
   } else {
     cx<T> w[R];
-    w[1] = twl<DIR>(tw, base);
-    w[2] = twl<DIR>(tw, 2 * base);
-    w[4] = twl<DIR>(tw, 4 * base);
+    w[1] = sd[0];
+    w[2] = sd[1];
+    w[4] = sd[2];
     w[3] = cmul(w[1], w[2]);
     w[5] = cmul(w[4], w[1]);
     w[6] = cmul(w[4], w[2]);
     w[7] = cmul(w[4], w[3]);
     if constexpr (R == 16) {
-      w[8] = twl<DIR>(tw, 8 * base);
+      w[8] = sd[3];
 #pragma unroll
       for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
     }
@@ -249,7 +280,7 @@ __device__ __forceinline__ void apply_tw(cx<T>* u, gptr<const cx<T>> __restrict_
 // write LDS.  Barriers are placed so one LDS buffer can be reused.
 template <int DIR, typename T, int N, int RMAX, int STAGE>
 __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__ lre, T* __restrict__ lim,
-                                               int t, gptr<const cx<T>> __restrict__ tw) {
+                                               int t, const StageSeeds<DIR, T, N, RMAX, STAGE>& sd) {
   using P = Plan<N, RMAX>;
   constexpr int R = P::radix(STAGE);
   constexpr int NS = P::ns(STAGE);
@@ -273,11 +304,7 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__
   }
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const int j = t + b * TPF;
-    if constexpr (NS > 1) {
-      const int k = j % NS;
-      apply_tw<DIR, R>(&u[b * R], tw, k * (N / (NS * R)));
-    }
+    if constexpr (NS > 1) apply_seeds<R>(&u[b * R], sd.w[b]);
     dft<DIR, R>(&u[b * R]);
   }
   if constexpr (LAST) {
@@ -302,10 +329,17 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__
   }
 }
 
-template <int DIR, typename T, int N, int RMAX, int STAGE = 0>
-__device__ __forceinline__ void fft_stages(cx<T> (&v)[RMAX], T* lre, T* lim, int t, gptr<const cx<T>> tw) {
-  stockham_stage<DIR, T, N, RMAX, STAGE>(v, lre, lim, t, tw);
-  if constexpr (STAGE + 1 < Plan<N, RMAX>::NSTAGE) fft_stages<DIR, T, N, RMAX, STAGE + 1>(v, lre, lim, t, tw);
+template <int DIR, typename T, int N, int RMAX, int STAGE>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[RMAX], T* lre, T* lim, int t, gptr<const cx<T>> tw,
+                                           const StageSeeds<DIR, T, N, RMAX, STAGE>& cur) {
+  if constexpr (STAGE + 1 < Plan<N, RMAX>::NSTAGE) {
+    StageSeeds<DIR, T, N, RMAX, STAGE + 1> nxt;
+    load_seeds<DIR, T, N, RMAX, STAGE + 1>(nxt, tw, t);
+    stockham_stage<DIR, T, N, RMAX, STAGE>(v, lre, lim, t, cur);
+    fft_stages<DIR, T, N, RMAX, STAGE + 1>(v, lre, lim, t, tw, nxt);
+  } else {
+    stockham_stage<DIR, T, N, RMAX, STAGE>(v, lre, lim, t, cur);
+  }
 }
 
 // Length-N transform of one signal held in pattern A by a team of Plan::TPF
@@ -317,7 +351,8 @@ __device__ __forceinline__ void fft(cx<T> (&v)[RMAX], T* lre, T* lim, int t, gpt
   // across unrelated work.
   gptr<const cx<T>> twp = tw;
   asm volatile("" : "+s"(twp) : : "memory");
-  fft_stages<DIR, T, N, RMAX, 0>(v, lre, lim, t, twp);
+  StageSeeds<DIR, T, N, RMAX, 0> none;   // stage 0 has no twiddles
+  fft_stages<DIR, T, N, RMAX, 0>(v, lre, lim, t, twp, none);
 }
 
 }  // namespace pm

@@ -38,7 +38,10 @@
 #define PM_ROW_WPE 2          // minimum waves per SIMD requested for the row pass
 #endif
 #ifndef PM_ROW_PREFETCH
-#define PM_ROW_PREFETCH 2     // pixel pairs of stress fetched ahead in the row pass
+#define PM_ROW_PREFETCH 1     // pixel pairs of stress fetched ahead in the row pass
+#endif
+#ifndef PM_STAGE_INFLIGHT
+#define PM_STAGE_INFLIGHT 6   // 16-byte loads per thread in flight while staging a row
 #endif
 #ifndef PM_COL_R32
 #define PM_COL_R32 16         // column-pass radix, FP32, L >= 2048
@@ -304,6 +307,13 @@ __device__ __forceinline__ cx<T> load_bin(P base, int m, int r, int c) {
   return cconj(ldc(base + pidx<WT, TSTRIDE>(L - m, r, c)));
 }
 
+// Largest divisor of n that is at most cap.
+constexpr int divisor_upto(int n, int cap) {
+  int d = cap < n ? cap : n;
+  while (n % d != 0) --d;
+  return d;
+}
+
 // Copy row r (0 or 1) of a row pair's slice of the half spectrum between HBM
 // and its LDS stage in 16-byte units: in tile j the row holds WT 3
 // contiguous complex values, and the stage keeps them in tile order.
@@ -314,15 +324,29 @@ __device__ __forceinline__ void stage_row(gptr<cx<T>> __restrict__ g, cx<T>* __r
   constexpr int NU = (L / 2 / WT) * UPT;
   static_assert((CPT * sizeof(cx<T>)) % 16 == 0, "a tile row must be a whole number of 16-byte units");
   using u4 = unsigned __attribute__((ext_vector_type(4)));
+  static_assert(NU % TPF == 0, "the copy must split evenly over the team");
+  constexpr int PER = NU / TPF;
   gptr<const u4> __restrict__ gs = (gptr<const u4>)g;
   gptr<u4> __restrict__ gd = (gptr<u4>)g;
   u4* __restrict__ ls = reinterpret_cast<u4*>(st);
-#pragma unroll 4
-  for (int u = t; u < NU; u += TPF) {
+  auto gidx = [&](int u) {
     const int j = u / UPT, k = u - j * UPT;
-    const unsigned gi = (unsigned)j * (L * WT * 3 * (int)sizeof(cx<T>) / 16) + r * UPT + k;
-    if constexpr (TO_LDS) ls[u] = gs[gi];
-    else gd[gi] = ls[u];
+    return (unsigned)j * (L * WT * 3 * (int)sizeof(cx<T>) / 16) + r * UPT + k;
+  };
+  if constexpr (TO_LDS) {
+    // loads are issued in groups of G before the group's LDS writes
+    constexpr int G = divisor_upto(PER, PM_STAGE_INFLIGHT);
+#pragma unroll
+    for (int i0 = 0; i0 < PER; i0 += G) {
+      u4 buf[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) buf[i] = gs[gidx(t + (i0 + i) * TPF)];
+#pragma unroll
+      for (int i = 0; i < G; ++i) ls[t + (i0 + i) * TPF] = buf[i];
+    }
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < PER; ++i) gd[gidx(t + i * TPF)] = ls[t + i * TPF];
   }
 }
 

@@ -4,12 +4,14 @@
 
 namespace pm {
 
-__device__ __forceinline__ double norm4(const double* a) {
+template <typename P>
+__device__ __forceinline__ double norm4(P a) {
   return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + 2.0 * a[3] * a[3]);
 }
 
 // Start a load step at E (also used when the device advances the ramp).
-__device__ __forceinline__ void begin_step(DevState* st, double E0, double E1, double E2, double mu) {
+template <typename P>
+__device__ __forceinline__ void begin_step(P st, double E0, double E1, double E2, double mu) {
   st->E[0] = E0; st->E[1] = E1; st->E[2] = E2;
   st->normE = sqrt(E0 * E0 + E1 * E1 + 2.0 * E2 * E2);
   st->floor_s = 1e-12 * mu * st->normE;
@@ -21,8 +23,8 @@ __device__ __forceinline__ void begin_step(DevState* st, double E0, double E1, d
 // the host reads the state; with one, the step's record is written and
 // marked pending: the output pass adds <eps> to it and the advance kernel
 // starts the next step from the current state.
-template <typename T>
-__device__ __forceinline__ void end_step(DevState* st, const Slot<T>& S, int status) {
+template <typename T, typename P>
+__device__ __forceinline__ void end_step(P st, const Slot<T>& S, int status) {
   st->status = status;
   st->halted = 1;
   if (S.rec == nullptr || S.E_path == nullptr) return;
@@ -44,15 +46,19 @@ __device__ __forceinline__ void end_step(DevState* st, const Slot<T>& S, int sta
 template <typename T>
 __global__ void __launch_bounds__(256) k_reduce(const Slot<T>* __restrict__ slots, int nblk) {
   const Slot<T>& S = slots[blockIdx.x];
-  DevState* st = S.st;
+  gptr<DevState> st = glb(S.st);
   if (st->halted) return;
   __shared__ double red[256][NSUM];
   double s[NSUM];
 #pragma unroll
   for (int i = 0; i < NSUM; ++i) s[i] = 0.0;
+  gptr<const double> part = glb(S.part);
+  // a fixed order for any nblk: thread t adds blocks t, t + 256, ...; the
+  // unrolled loop keeps several loads in flight
+#pragma unroll 8
   for (int b = threadIdx.x; b < nblk; b += 256) {
 #pragma unroll
-    for (int i = 0; i < NSUM; ++i) s[i] += S.part[(long)b * NPART + i];
+    for (int i = 0; i < NSUM; ++i) s[i] += part[(long)b * NPART + i];
   }
 #pragma unroll
   for (int i = 0; i < NSUM; ++i) red[threadIdx.x][i] = s[i];
@@ -106,11 +112,12 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, int L, int dbps, int force) {
   const Slot<T>& S = slots[blockIdx.x / dbps];
   const int lb = blockIdx.x % dbps;
-  if (!force && (S.st->halted || !S.st->need_eq)) return;
+  gptr<const DevState> st = glb(S.st);
+  if (!force && (st->halted || !st->need_eq)) return;
   const long npx = (long)L * L;
-  const T* __restrict__ s11 = S.sig;
-  const T* __restrict__ s22 = S.sig + npx;
-  const T* __restrict__ s12 = S.sig + 3 * npx;
+  gptr<const T> __restrict__ s11 = glb(S.sig);
+  gptr<const T> __restrict__ s22 = s11 + npx;
+  gptr<const T> __restrict__ s12 = s11 + 3 * npx;
   double acc[1] = {0.0};
   for (long ix = (long)lb * blockDim.x + threadIdx.x; ix < npx; ix += (long)dbps * blockDim.x) {
     const int x1 = (int)(ix & (L - 1));
@@ -121,7 +128,7 @@ __global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, 
     const double d2 = ((double)s12[ix] - (double)s12[i1]) + ((double)s22[ix] - (double)s22[i2]);
     acc[0] += d1 * d1 + d2 * d2;
   }
-  block_reduce_store<1>(acc, S.part2 + lb);
+  block_reduce_store<1>(acc, glb(S.part2) + lb);
 }
 
 // Equilibrium indicator eta_1 from the residual partials; ends the step on
@@ -129,11 +136,13 @@ __global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, 
 template <typename T>
 __global__ void __launch_bounds__(256) k_reduce_div(const Slot<T>* __restrict__ slots, int nblk, int force) {
   const Slot<T>& S = slots[blockIdx.x];
-  DevState* st = S.st;
+  gptr<DevState> st = glb(S.st);
   if (!force && (st->halted || !st->need_eq)) return;
   __shared__ double red[256];
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 256) s += S.part2[b];
+  gptr<const double> part2 = glb(S.part2);
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part2[b];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
