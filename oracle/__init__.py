@@ -13,6 +13,8 @@ Modules
     alm     the augmented-Lagrangian / Uzawa iteration, its convergence
             indicators (Sec. 2, "Convergence issues") and the load ramp.
     brute   FFT-free brute-force solvers for tiny grids (L <= 8).
+    dg2     the DG2 average of the four sign variants of the Green tensor
+            (Sec. 2, "Discrete Green functions").
 
 Every function states the passage it follows.  Functions without an
 independent pin say "parity unpinned" in their docstring.
