@@ -281,7 +281,14 @@ typedef struct pm_slot_info {
   int32_t steps_done;        /* records 0 .. steps_done-1 are final */
   int32_t finished;          /* 1: all steps done, or stopped at a non-finite value */
   int32_t last_status;       /* status of the last finished step (0 if none) */
+  int32_t held;              /* 1: waiting after step steps_done-1 (PM_ADMIT_HOLD) */
 } pm_slot_info;
+
+/* Admission flag: after each load step (but the last) the slot waits with the
+ * converged fields of that step until pm_batch_resume; pm_batch_fetch then
+ * returns exactly that step's fields.  Used to combine several slots step by
+ * step (DG2). */
+#define PM_ADMIT_HOLD 1
 
 /* Fixed part of the pool for max_slots slots (slot states, the device slot
  * table and the twiddle / momentum tables of every grid size). */
@@ -301,10 +308,15 @@ int pm_batch_create(pm_batch** out, void* d_pool, size_t pool_bytes, int32_t max
  * nonzero finite norm), copied.  On success *slot receives the slot id.
  * The first step starts from the uniform state of that step's E (as the
  * first pm_solver_step).  The work is queued on the batch's stream; it
- * runs with the next ticks.  Returns PM_EBUSY (nothing changed) when the
- * pool or the slot table is full. */
+ * runs with the next ticks.  flags: 0 or PM_ADMIT_HOLD.  Returns PM_EBUSY
+ * (nothing changed) when the pool or the slot table is full. */
 int pm_batch_admit(pm_batch* batch, const pm_params* params, const uint8_t* d_void_mask, int32_t nsteps,
-                   const double* E_path, int32_t* slot);
+                   const double* E_path, int32_t flags, int32_t* slot);
+
+/* Start the next load step of a slot admitted with PM_ADMIT_HOLD that is
+ * waiting (pm_slot_info.held); queued on the batch's stream.  PM_EINVAL if
+ * the slot is not waiting. */
+int pm_batch_resume(pm_batch* batch, int32_t slot);
 
 /* Run iters augmented-Lagrangian iterations on every running slot, then end
  * the load steps that finished (output pass for <eps>, record, start of the
@@ -327,6 +339,39 @@ int pm_batch_fetch(pm_batch* batch, int32_t slot, pm_step_out* out);
  * stopped.  Blocking (waits for queued work). */
 int pm_batch_release(pm_batch* batch, int32_t slot);
 int pm_batch_destroy(pm_batch* batch);
+
+
+/* ------------------------------------------------------------------------
+ * DG2 (Sec. 2, "Discrete Green functions"): the same system is solved to
+ * convergence with the Green tensor of eq. 3 taken at (q1, q2), (-q1, -q2),
+ * (-q1, q2) and (q1, -q2) (green_variant 0..3), and the four strain fields
+ * are averaged.  pm_dg2_combine forms, per pixel, the average strain, the
+ * Hencky-Mises stress of the average (zero on voids), the average of the
+ * four stresses and the plastic mask of the average (matrix pixels with
+ * 3 mu eps_eq > Y), and the FP64 means of the three fields.
+ * ---------------------------------------------------------------------- */
+typedef struct pm_dg2_out {
+  void* eps;               /* device, 4 planes (11, 22, 33, 12), or NULL */
+  void* sigma_of_avg;      /* device, 4 planes, or NULL */
+  void* sigma_avg;         /* device, 4 planes, or NULL (needs d_sigma) */
+  uint8_t* plastic;        /* device, L x L, or NULL */
+  double eps_mean[4];
+  double sigma_of_avg_mean[4];
+  double sigma_avg_mean[4];   /* zeros when d_sigma is NULL */
+  double plastic_fraction;
+} pm_dg2_out;
+
+/* Device workspace pm_dg2_combine needs for these parameters (partial sums);
+ * 0 if params are invalid. */
+size_t pm_dg2_workspace_bytes(const pm_params* params);
+
+/* params: L, mu, lambda, Y and precision of the four solves.  d_eps[v],
+ * d_sigma[v]: device fields (4 planes each, field precision) of variant v;
+ * d_sigma may be NULL.  Queued on stream, then synchronised for the means.
+ * Inputs and outputs may not overlap. */
+int pm_dg2_combine(const pm_params* params, const uint8_t* d_void_mask, const void* const d_eps[4],
+                   const void* const d_sigma[4], void* d_workspace, size_t workspace_bytes, pm_dg2_out* out,
+                   void* stream);
 
 #ifdef __cplusplus
 }

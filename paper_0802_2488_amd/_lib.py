@@ -59,10 +59,21 @@ class PmSlotInfo(ctypes.Structure):
     _fields_ = [
         ("L", ctypes.c_int32), ("precision", ctypes.c_int32), ("nsteps", ctypes.c_int32),
         ("steps_done", ctypes.c_int32), ("finished", ctypes.c_int32), ("last_status", ctypes.c_int32),
+        ("held", ctypes.c_int32),
     ]
 
 
 PM_STEP_CONVERGED, PM_STEP_NOCONV, PM_STEP_NAN = 1, 2, 3
+PM_ADMIT_HOLD = 1
+
+
+class PmDg2Out(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_void_p), ("sigma_of_avg", ctypes.c_void_p), ("sigma_avg", ctypes.c_void_p),
+        ("plastic", ctypes.c_void_p),
+        ("eps_mean", ctypes.c_double * 4), ("sigma_of_avg_mean", ctypes.c_double * 4),
+        ("sigma_avg_mean", ctypes.c_double * 4), ("plastic_fraction", ctypes.c_double),
+    ]
 
 # (name, restype, argtypes) of every entry point in include/pm.h
 SIGNATURES = [
@@ -89,7 +100,8 @@ SIGNATURES = [
      [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p]),
     ("pm_batch_admit", ctypes.c_int,
      [ctypes.c_void_p, ctypes.POINTER(PmParams), ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
-      ctypes.POINTER(ctypes.c_int32)]),
+      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    ("pm_batch_resume", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("pm_batch_tick", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     ("pm_batch_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(PmSlotInfo)]),
     ("pm_batch_records", ctypes.c_int,
@@ -97,6 +109,10 @@ SIGNATURES = [
     ("pm_batch_fetch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(PmStepOut)]),
     ("pm_batch_release", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("pm_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("pm_dg2_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(PmParams)]),
+    ("pm_dg2_combine", ctypes.c_int,
+     [ctypes.POINTER(PmParams), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+      ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(PmDg2Out), ctypes.c_void_p]),
 ]
 
 _lib = None

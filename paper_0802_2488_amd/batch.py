@@ -73,15 +73,17 @@ class Batch:
         except Exception:
             pass
 
-    def admit(self, mask: torch.Tensor, params: PmParams, E_path) -> int | None:
-        """Slot id, or None when the pool or the slot table is full."""
+    def admit(self, mask: torch.Tensor, params: PmParams, E_path, hold: bool = False) -> int | None:
+        """Slot id, or None when the pool or the slot table is full.  hold:
+        wait after every load step until resume() (fields of that step)."""
         m = mask.to(device=self.device, dtype=torch.uint8).contiguous()
         if tuple(m.shape) != (params.L, params.L):
             raise ValueError(f"mask shape {tuple(m.shape)} != ({params.L}, {params.L})")
         E = np.ascontiguousarray(np.asarray(E_path, dtype=np.float64).reshape(-1, 3))
         slot = ctypes.c_int32(-1)
         rc = lib().pm_batch_admit(self.handle, ctypes.byref(params), m.data_ptr(), E.shape[0],
-                                  E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(slot))
+                                  E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  _lib.PM_ADMIT_HOLD if hold else 0, ctypes.byref(slot))
         if rc == _lib.PM_EBUSY:
             return None
         check(rc, "pm_batch_admit")
@@ -121,6 +123,9 @@ class Batch:
             out.sigma, out.eps, out.plastic = sig.data_ptr(), eps.data_ptr(), pl.data_ptr()
         check(lib().pm_batch_fetch(self.handle, slot, ctypes.byref(out)), "pm_batch_fetch")
         return sig, eps, pl, out
+
+    def resume(self, slot: int):
+        check(lib().pm_batch_resume(self.handle, slot), "pm_batch_resume")
 
     def release(self, slot: int):
         check(lib().pm_batch_release(self.handle, slot), "pm_batch_release")

@@ -237,7 +237,7 @@ int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
     if (rc != PM_OK) return rc;
     s->started = true;
   }
-  PM_HIP(pm::launch_begin(s->st, E, s->p.mu, 0, 1, s->stream));
+  PM_HIP(pm::launch_begin(s->st, E, s->p.mu, 0, 1, 0, s->stream));
   const int max_iter = s->p.max_iter;
   int issued = 0, slot = 0, pend = -1, fin = -1;
   while (fin < 0 && s->timing) {
@@ -482,6 +482,52 @@ int pm_bernoulli_mask(uint8_t* dst, int32_t L, double f, uint64_t seed, int32_t 
     const uint64_t z = pmh::splitmix64(seed ^ pmh::splitmix64((uint64_t)p));
     dst[p] = ((double)(z >> 11) * 0x1.0p-53) < f ? 1 : 0;
   }
+  return PM_OK;
+}
+
+size_t pm_dg2_workspace_bytes(const pm_params* params) {
+  pm_params q;
+  if (pmh::check_params(params, &q) != PM_OK) return 0;
+  return ((size_t)pm::dg2_blocks(q.L) * 16 + 16) * sizeof(double);
+}
+
+int pm_dg2_combine(const pm_params* params, const uint8_t* d_void_mask, const void* const d_eps[4],
+                   const void* const d_sigma[4], void* d_workspace, size_t workspace_bytes, pm_dg2_out* out,
+                   void* stream) {
+  pm_params q;
+  int rc = pmh::check_params(params, &q);
+  if (rc != PM_OK) return rc;
+  if (!d_void_mask || !d_eps || !d_workspace || !out) return fail(PM_EINVAL, "NULL argument");
+  for (int v = 0; v < 4; ++v) {
+    if (!d_eps[v]) return fail(PM_EINVAL, "d_eps[%d] is NULL", v);
+    if (d_sigma && !d_sigma[v]) return fail(PM_EINVAL, "d_sigma[%d] is NULL", v);
+  }
+  const int nblk = pm::dg2_blocks(q.L);
+  const size_t need = ((size_t)nblk * 16 + 16) * sizeof(double);
+  if (workspace_bytes < need) return fail(PM_EINVAL, "workspace of %zu bytes is smaller than the %zu required",
+                                          workspace_bytes, need);
+  if (((uintptr_t)d_workspace) % 8 != 0) return fail(PM_EINVAL, "workspace must be 8-byte aligned");
+  const pm::DevParams prm = pmh::dev_params(q);
+  hipStream_t st = (hipStream_t)stream;
+  double* part = (double*)d_workspace;
+  if (q.precision == PM_FP64) {
+    PM_HIP(pm::launch_dg2<double>(q.L, prm, d_void_mask, (const double* const*)d_eps,
+                                  (const double* const*)d_sigma, (double*)out->eps, (double*)out->sigma_of_avg,
+                                  (double*)out->sigma_avg, out->plastic, part, nblk, st));
+  } else {
+    PM_HIP(pm::launch_dg2<float>(q.L, prm, d_void_mask, (const float* const*)d_eps, (const float* const*)d_sigma,
+                                 (float*)out->eps, (float*)out->sigma_of_avg, (float*)out->sigma_avg, out->plastic,
+                                 part, nblk, st));
+  }
+  double means[13];
+  PM_HIP(hipMemcpyAsync(means, part + (size_t)nblk * 16, sizeof means, hipMemcpyDeviceToHost, st));
+  PM_HIP(hipStreamSynchronize(st));
+  for (int c = 0; c < 4; ++c) {
+    out->eps_mean[c] = means[c];
+    out->sigma_of_avg_mean[c] = means[4 + c];
+    out->sigma_avg_mean[c] = means[8 + c];
+  }
+  out->plastic_fraction = means[12];
   return PM_OK;
 }
 

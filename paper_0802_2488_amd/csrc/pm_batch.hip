@@ -130,6 +130,7 @@ struct HostSlot {
   pm_params q{};
   int group = 0;
   int nsteps = 0;
+  int hold = 0;              // PM_ADMIT_HOLD
   size_t off = 0;
   SlotLayout sl{};
   std::vector<double> E;               // host copy of the ramp (source of the upload)
@@ -254,7 +255,7 @@ int admit_impl(pm_batch* b, int i, const uint8_t* mask) {
   memcpy(h.desc, &S, SLOT_DESC);
   PM_HIP(hipMemcpyAsync(region + h.sl.E, h.E.data(), h.E.size() * sizeof(double), hipMemcpyHostToDevice, b->stream));
   PM_HIP(hipMemcpyAsync(region + h.sl.desc, h.desc, SLOT_DESC, hipMemcpyHostToDevice, b->stream));
-  PM_HIP(pm::launch_begin(dev_state(b, i), h.E.data(), h.q.mu, 0, h.nsteps, b->stream));
+  PM_HIP(pm::launch_begin(dev_state(b, i), h.E.data(), h.q.mu, 0, h.nsteps, h.hold, b->stream));
   // uniform start at E_1 (the state's E), as the first step of a solver
   const pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_ALL, 1.0, nullptr);
   PM_HIP(pm::launch_row<T>(L, pm::ROW_INIT, own_desc<T>(b, i), 1, x, b->stream));
@@ -296,7 +297,7 @@ int check_slot(pm_batch* b, int32_t slot) {
 }
 
 int steps_done(const HostSlot& h) {
-  if (h.st.finished) return h.st.step + 1;
+  if (h.st.finished || h.st.held) return h.st.step + 1;
   return h.st.step;
 }
 
@@ -359,9 +360,10 @@ int pm_batch_create(pm_batch** out, void* d_pool, size_t pool_bytes, int32_t max
 }
 
 int pm_batch_admit(pm_batch* b, const pm_params* params, const uint8_t* d_void_mask, int32_t nsteps,
-                   const double* E_path, int32_t* slot) {
+                   const double* E_path, int32_t flags, int32_t* slot) {
   if (!b || !slot) return fail(PM_EINVAL, "batch and slot must not be NULL");
   *slot = -1;
+  if (flags & ~PM_ADMIT_HOLD) return fail(PM_EINVAL, "unknown admission flags 0x%x", flags);
   pm_params q;
   int rc = pmh::check_params(params, &q);
   if (rc != PM_OK) return rc;
@@ -396,6 +398,7 @@ int pm_batch_admit(pm_batch* b, const pm_params* params, const uint8_t* d_void_m
   h.q = q;
   h.group = g;
   h.nsteps = nsteps;
+  h.hold = (flags & PM_ADMIT_HOLD) ? 1 : 0;
   h.off = off;
   h.sl = sl;
   h.E.assign(E_path, E_path + 3 * (size_t)nsteps);
@@ -465,6 +468,21 @@ int pm_batch_poll(pm_batch* b, int32_t slot, pm_slot_info* info) {
   info->steps_done = steps_done(h);
   info->finished = h.finished ? 1 : 0;
   info->last_status = info->steps_done > 0 ? h.st.status : 0;
+  info->held = (!h.finished && h.st.held) ? 1 : 0;
+  return PM_OK;
+}
+
+int pm_batch_resume(pm_batch* b, int32_t slot) {
+  int rc = check_slot(b, slot);
+  if (rc != PM_OK) return rc;
+  HostSlot& h = b->slots[slot];
+  if (h.finished || !h.st.held) return fail(PM_EINVAL, "slot %d is not waiting after a load step", slot);
+  const int next = h.st.step + 1;
+  if (hipSetDevice(b->device) != hipSuccess) return fail(PM_EDEVICE, "hipSetDevice failed");
+  PM_HIP(pm::launch_begin(dev_state(b, slot), h.E.data() + 3 * (size_t)next, h.q.mu, next, h.nsteps, h.hold,
+                          b->stream));
+  h.st.held = 0;
+  h.st.step = next;
   return PM_OK;
 }
 

@@ -42,6 +42,8 @@ struct DevState {
   int32_t step, nsteps;        // load-ramp position when the device advances steps itself
   int32_t finished;            // all steps of the ramp done
   int32_t pending;             // a step ended; its record waits for the output pass
+  int32_t hold;                // wait after every step until the host resumes the slot
+  int32_t held;                // waiting (step ended, record complete, next step not begun)
 };
 
 struct DevParams {
@@ -111,8 +113,13 @@ template <typename T>
 hipError_t launch_reduce_emit(const Slot<T>* slots, int nslots, int nblk, int gate, hipStream_t s);
 template <typename T>
 hipError_t launch_advance(const Slot<T>* slots, int nslots, hipStream_t s);
-hipError_t launch_begin(DevState* st, const double* E, double mu, int32_t step, int32_t nsteps,
+hipError_t launch_begin(DevState* st, const double* E, double mu, int32_t step, int32_t nsteps, int32_t hold,
                         hipStream_t s);
+template <typename T>
+hipError_t launch_dg2(int L, const DevParams& prm, const uint8_t* mask, const T* const* eps4, const T* const* sig4,
+                      T* eps_out, T* soa_out, T* sav_out, uint8_t* pl_out, double* partials, int nblk,
+                      hipStream_t s);
+int dg2_blocks(int L);
 hipError_t launch_mask(uint8_t* out, long npx, double f, uint64_t seed, hipStream_t s);
 
 }  // namespace pm

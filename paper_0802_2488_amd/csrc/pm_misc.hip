@@ -206,17 +206,24 @@ __global__ void k_advance(const Slot<T>* __restrict__ slots, int nslots) {
     st->finished = 1;
     return;
   }
+  if (st->hold) {
+    st->held = 1;   // the host reads the step's fields, then resumes the slot
+    return;
+  }
   st->step = next;
   begin_step(st, S.E_path[3 * next], S.E_path[3 * next + 1], S.E_path[3 * next + 2], S.prm.mu);
 }
 
-__global__ void k_begin(DevState* st, double E0, double E1, double E2, double mu, int32_t step, int32_t nsteps) {
+__global__ void k_begin(DevState* st, double E0, double E1, double E2, double mu, int32_t step, int32_t nsteps,
+                        int32_t hold) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     begin_step(st, E0, E1, E2, mu);
     st->step = step;
     st->nsteps = nsteps;
     st->finished = 0;
     st->pending = 0;
+    st->hold = hold;
+    st->held = 0;
   }
 }
 
@@ -281,8 +288,9 @@ PM_INST(float)
 PM_INST(double)
 #undef PM_INST
 
-hipError_t launch_begin(DevState* st, const double* E, double mu, int32_t step, int32_t nsteps, hipStream_t s) {
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, st, E[0], E[1], E[2], mu, step, nsteps);
+hipError_t launch_begin(DevState* st, const double* E, double mu, int32_t step, int32_t nsteps, int32_t hold,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, st, E[0], E[1], E[2], mu, step, nsteps, hold);
   return hipGetLastError();
 }
 

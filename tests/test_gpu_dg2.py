@@ -1,0 +1,144 @@
+"""GPU: DG2 (Sec. 2, "Discrete Green functions") through the C ABI.
+
+The combination kernel against the oracle's average; the whole DG2 driver
+(four held batch slots) against the oracle, iteration-locked, in FP64; the
+mirror symmetry DG2 restores; and the hold / resume protocol of the batch
+engine, which must not change any result.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import alm  # noqa: E402
+from oracle import dg2 as odg2  # noqa: E402
+from paper_0802_2488_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0802_2488_amd import batch as pmb  # noqa: E402
+from paper_0802_2488_amd import dg2 as pdg2  # noqa: E402
+from paper_0802_2488_amd import solver as pms  # noqa: E402
+from paper_0802_2488_amd._lib import PmError  # noqa: E402
+
+
+def params(L, precision, tol=0.0, max_iter=9):
+    return pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=tol, max_iter=max_iter, precision=precision)
+
+
+def t33(planes):
+    return alm.from_voigt4(np.moveaxis(planes.detach().cpu().double().numpy(), 0, -1))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("L,precision,tol", [(16, "fp64", 1e-14), (64, "fp64", 1e-14), (128, "fp32", 1e-6),
+                                             (1024, "fp32", 1e-6)])
+def test_combine_matches_oracle(L, precision, tol):
+    rng = np.random.default_rng(L)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    mask = synth.bernoulli_mask(L, 0.25, 9)
+    eps4 = rng.normal(size=(4, 4, L, L)) * 0.6
+    sig4 = rng.normal(size=(4, 4, L, L))
+    te = [torch.tensor(e, dtype=dt, device="cuda") for e in eps4]
+    ts = [torch.tensor(s, dtype=dt, device="cuda") for s in sig4]
+    r = pdg2.combine(params(L, precision), torch.tensor(mask, device="cuda"), te, ts)
+    e4 = np.stack([t33(x) for x in te])       # the inputs as the device holds them
+    s4 = np.stack([t33(x) for x in ts])
+    eps, soa, sav, pl, mg = odg2.combine(mask, e4, s4, 1.0, 2.0, 1.0)
+    assert rel(t33(r.eps), eps) <= tol
+    assert rel(t33(r.sigma_of_avg), soa) <= tol * 10
+    assert rel(t33(r.sigma_avg), sav) <= tol
+    band = np.abs(mg) <= 1e-5
+    assert np.array_equal(r.plastic.cpu().numpy().astype(bool)[~band], pl[~band])
+    np.testing.assert_allclose(r.eps_mean, alm.voigt4(eps.mean(axis=(0, 1))), rtol=tol * 10, atol=tol)
+    np.testing.assert_allclose(r.sigma_avg_mean, alm.voigt4(sav.mean(axis=(0, 1))), rtol=tol * 10, atol=tol)
+    assert abs(r.plastic_fraction - pl.mean()) <= 1e-5 + band.mean()
+
+
+def test_dg2_fp64_iteration_locked_against_oracle():
+    L, iters = 32, 9
+    mask = synth.bernoulli_mask(L, 0.2, 7)
+    path = [(0.3, 0.3, 0.0), (0.5, 0.45, 0.05)]
+    got = pdg2.solve_path(torch.tensor(mask, device="cuda"), params(L, "fp64", max_iter=iters), path, tick_iters=4)
+    ref = odg2.solve_path(mask, alm.Params(L=L), path, fixed_iters=[[iters] * 2] * 4)
+    for g, o in zip(got, ref):
+        assert all(r.iters == iters for r in g.records)
+        assert rel(t33(g.eps), o.eps) <= 1e-10
+        assert rel(t33(g.sigma_of_avg), o.sigma_of_avg) <= 1e-10
+        assert rel(t33(g.sigma_avg), o.sigma_avg) <= 1e-10
+        band = np.abs(o.margin) <= 1e-5
+        assert np.array_equal(g.plastic.cpu().numpy().astype(bool)[~band], o.plastic[~band])
+        np.testing.assert_allclose(g.sigma_avg_mean, alm.voigt4(o.sigma_avg.mean(axis=(0, 1))), rtol=1e-10,
+                                   atol=1e-13)
+
+
+def test_dg2_commutes_with_the_x1_mirror_on_gpu():
+    L = 64
+    mask = synth.bernoulli_mask(L, 0.25, 11)
+    mir = mask[:, (-np.arange(L)) % L]
+    path = [(0.4, 0.2, 0.1)]
+    p = params(L, "fp64", max_iter=20)
+    a = pdg2.solve_path(torch.tensor(mask, device="cuda"), p, path)[0]
+    b = pdg2.solve_path(torch.tensor(mir, device="cuda"), p, path)[0]
+    ea = a.eps.cpu().numpy()[:, :, (-np.arange(L)) % L]
+    assert np.abs(b.eps.cpu().numpy() - ea).max() <= 1e-10 * np.abs(ea).max()
+    # a single variant is not mirror symmetric
+    s = [pms.Solver(torch.tensor(m, device="cuda"), p) for m in (mask, mir)]
+    r = [x.step(path[0]) for x in s]
+    for x in s:
+        x.close()
+    e0 = r[0].eps.cpu().numpy()[:, :, (-np.arange(L)) % L]
+    assert np.abs(r[1].eps.cpu().numpy() - e0).max() > 1e-4
+
+
+def test_hold_and_resume_change_no_result():
+    L = 32
+    mask = torch.tensor(synth.bernoulli_mask(L, 0.15, 2), device="cuda")
+    p = params(L, "fp32", tol=1e-6, max_iter=200)
+    path = synth.load_path("shear", 10, 4.0)[:3]
+    b = pmb.Batch(pmb.overhead_bytes(2) + 2 * pmb.slot_bytes(p, 3), max_slots=2)
+    free = b.admit(mask, p, path)
+    held = b.admit(mask, p, path, hold=True)
+    with pytest.raises(PmError):
+        b.resume(free)                       # never waits
+    for step in range(3):
+        for _ in range(100):
+            b.tick(8)
+            if b.poll(held)["steps_done"] > step:
+                break
+        info = b.poll(held)
+        assert info["steps_done"] == step + 1
+        assert info["held"] == (1 if step < 2 else 0)
+        if step < 2:
+            b.resume(held)
+            with pytest.raises(PmError):
+                b.resume(held)               # already resumed
+    for _ in range(200):
+        if b.tick(8) == 0:
+            break
+    ra, rb = b.records(free), b.records(held)
+    assert len(ra) == len(rb) == 3
+    for x, y in zip(ra, rb):
+        assert x.iters == y.iters and np.array_equal(x.sigma_mean, y.sigma_mean)
+        assert np.array_equal(x.eps_mean, y.eps_mean)
+    b.close()
+
+
+def test_dg2_invalid_arguments():
+    L = 16
+    p = params(L, "fp32")
+    m = torch.zeros((L, L), dtype=torch.uint8, device="cuda")
+    e = [torch.zeros((4, L, L), device="cuda") for _ in range(4)]
+    with pytest.raises(ValueError):
+        pdg2.combine(p, m, [x.double() for x in e])          # wrong precision
+    bad = params(L, "fp32")
+    bad.L = 48
+    with pytest.raises(PmError):
+        pdg2.combine(bad, torch.zeros((48, 48), dtype=torch.uint8, device="cuda"),
+                     [torch.zeros((4, 48, 48), device="cuda") for _ in range(4)])
