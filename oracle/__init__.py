@@ -15,6 +15,7 @@ Modules
     brute   FFT-free brute-force solvers for tiny grids (L <= 8).
     dg2     the DG2 average of the four sign variants of the Green tensor
             (Sec. 2, "Discrete Green functions").
+    clusters  void / plastic clusters and the Sec. 3 indicators.
 
 Every function states the passage it follows.  Functions without an
 independent pin say "parity unpinned" in their docstring.

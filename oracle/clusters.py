@@ -1,0 +1,173 @@
+"""Void and plastic clusters of a solved grid (Sec. 3).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Phases: void (mask = 1), plastic (matrix pixels on the yield surface, the
+plastic mask of a solve) and elastic.  Clusters are sets of pixels of one
+phase connected through nearest neighbours (the Hoshen-Kopelman labelling
+the paper uses); the "void-plastic" phase is the union of voids and plastic
+pixels.  A plastic cluster that touches no void is then connected to its
+nearest void, so every cluster holds at least one void.
+
+Readings (the paper is silent on them):
+  * the lattice is periodic (the computations are on a periodic cell), so
+    neighbours wrap around the edges;
+  * "nearest" is the periodic Euclidean distance between pixel centres,
+    from any pixel of the cluster to any void pixel; ties go to the void
+    pixel of smallest index x2 * L + x1;
+  * a cluster's label is the smallest pixel index it holds (canonical, so
+    labellings compare exactly);
+  * the largest cluster "spans" an axis when it occupies every column
+    (every row) of the lattice.
+
+Indicators of Sec. 3: the void-plastic fraction v_p and f_p = v_p / (1 - f),
+v_max (largest void-plastic cluster / L^2), i (void clusters with no plastic
+neighbour / void clusters) and n (void-plastic clusters / void clusters of
+the unloaded grid, i.e. the void phase alone).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy import ndimage
+
+
+def _uf_find(parent, x):
+    while parent[x] != x:
+        parent[x] = parent[parent[x]]
+        x = parent[x]
+    return x
+
+
+def label_periodic(phase: np.ndarray) -> np.ndarray:
+    """Periodic 4-connected components; label = smallest pixel index, -1 outside."""
+    phase = np.asarray(phase).astype(bool)
+    L = phase.shape[0]
+    lab, n = ndimage.label(phase, structure=[[0, 1, 0], [1, 1, 1], [0, 1, 0]])
+    parent = list(range(n + 1))
+
+    def union(a, b):
+        a, b = _uf_find(parent, a), _uf_find(parent, b)
+        if a != b:
+            parent[max(a, b)] = min(a, b)
+
+    for i in range(L):   # wrap-around bonds
+        if lab[i, 0] and lab[i, L - 1]:
+            union(lab[i, 0], lab[i, L - 1])
+        if lab[0, i] and lab[L - 1, i]:
+            union(lab[0, i], lab[L - 1, i])
+    root = np.array([_uf_find(parent, k) for k in range(n + 1)])
+    comp = root[lab]
+    out = np.full(L * L, -1, dtype=np.int64)
+    flat = comp.ravel()
+    idx = np.arange(L * L)
+    inside = flat > 0
+    # canonical label: smallest pixel index of the component
+    mins = np.full(n + 1, L * L, dtype=np.int64)
+    np.minimum.at(mins, flat[inside], idx[inside])
+    out[inside] = mins[flat[inside]]
+    return out.reshape(L, L)
+
+
+def label_bfs(phase: np.ndarray) -> np.ndarray:
+    """The same labelling by breadth-first search (independent check, small L)."""
+    phase = np.asarray(phase).astype(bool)
+    L = phase.shape[0]
+    out = np.full((L, L), -1, dtype=np.int64)
+    for p in range(L * L):
+        y, x = divmod(p, L)
+        if not phase[y, x] or out[y, x] >= 0:
+            continue
+        out[y, x] = p          # p is the smallest index of its component (visited in order)
+        stack = [(y, x)]
+        while stack:
+            cy, cx = stack.pop()
+            for ny, nx in ((cy, (cx + 1) % L), (cy, (cx - 1) % L), ((cy + 1) % L, cx), ((cy - 1) % L, cx)):
+                if phase[ny, nx] and out[ny, nx] < 0:
+                    out[ny, nx] = p
+                    stack.append((ny, nx))
+    return out
+
+
+def nearest_void(L, pixels, void_idx):
+    """(d2, void index) of the nearest void pixel to any of `pixels` (flat
+    indices), periodic Euclidean distance, ties to the smallest void index."""
+    py, px = np.divmod(np.asarray(pixels), L)
+    vy, vx = np.divmod(np.asarray(void_idx), L)
+    dy = np.abs(py[:, None] - vy[None, :])
+    dx = np.abs(px[:, None] - vx[None, :])
+    dy = np.minimum(dy, L - dy)
+    dx = np.minimum(dx, L - dx)
+    d2 = (dx * dx + dy * dy).min(axis=0)          # per void pixel: distance to the cluster
+    best = d2.min()
+    v = np.asarray(void_idx)[d2 == best].min()
+    return int(best), int(v)
+
+
+def analyze(void: np.ndarray, plastic: np.ndarray):
+    """Cluster labels (after attachment) and the counts behind the indicators."""
+    void = np.asarray(void).astype(bool)
+    plastic = np.asarray(plastic).astype(bool) & ~void
+    L = void.shape[0]
+    npx = L * L
+    vp = void | plastic
+    void_lab = label_periodic(void)
+    raw = label_periodic(vp)
+    roots = np.unique(raw[raw >= 0])
+    flat = raw.ravel()
+    vflat, pflat = void.ravel(), plastic.ravel()
+    has_void = {int(r): bool(vflat[flat == r].any()) for r in roots}
+    has_plastic = {int(r): bool(pflat[flat == r].any()) for r in roots}
+    void_idx = np.flatnonzero(vflat)
+    # attach plastic-only clusters to the cluster of their nearest void
+    parent = {int(r): int(r) for r in roots}
+
+    def find(x):
+        while parent[x] != x:
+            x = parent[x]
+        return x
+
+    plastic_only = [int(r) for r in roots if not has_void[int(r)]]
+    if len(void_idx):
+        for r in plastic_only:
+            _, v = nearest_void(L, np.flatnonzero(flat == r), void_idx)
+            a, b = find(r), find(int(flat[v]))
+            if a != b:
+                parent[max(a, b)] = min(a, b)
+    final = np.full(npx, -1, dtype=np.int64)
+    comp = np.array([find(int(x)) if x >= 0 else -1 for x in flat])
+    inside = comp >= 0
+    # canonical labels again: smallest pixel index of each merged component
+    for c in np.unique(comp[inside]):
+        sel = comp == c
+        final[sel] = np.flatnonzero(sel).min()
+    final = final.reshape(L, L)
+    labs, sizes = np.unique(final[final >= 0], return_counts=True)
+    if len(labs):
+        big = sizes.max()
+        largest_label = int(labs[sizes == big].min())
+        cells = final == largest_label
+        spans_x1 = bool(cells.any(axis=0).all())
+        spans_x2 = bool(cells.any(axis=1).all())
+    else:
+        big, largest_label, spans_x1, spans_x2 = 0, -1, False, False
+    n_void_clusters = len(np.unique(void_lab[void_lab >= 0]))
+    stats = dict(
+        n_void=int(void.sum()), n_plastic=int(plastic.sum()),
+        n_void_clusters=n_void_clusters,
+        n_clusters_raw=len(roots),
+        n_isolated_void_clusters=sum(1 for r in roots if has_void[int(r)] and not has_plastic[int(r)]),
+        n_plastic_only_clusters=len(plastic_only),
+        n_clusters=len(labs), largest=int(big), largest_label=largest_label,
+        spans_x1=spans_x1, spans_x2=spans_x2,
+    )
+    return final, stats
+
+
+def indicators(stats, L, f=None):
+    """Sec. 3 indicators from the counts (f defaults to the void fraction)."""
+    npx = L * L
+    f = stats["n_void"] / npx if f is None else f
+    vp = (stats["n_void"] + stats["n_plastic"]) / npx
+    nvc = max(stats["n_void_clusters"], 1)
+    return dict(v_p=vp, f_p=vp / (1.0 - f), v_max=stats["largest"] / npx,
+                i=stats["n_isolated_void_clusters"] / nvc, n=stats["n_clusters"] / nvc)

@@ -1,0 +1,110 @@
+"""Pins of the cluster-analysis oracle (Sec. 3).
+
+Labelling: the scipy-based periodic labelling against an independent
+breadth-first search, and against scipy's own non-periodic labelling where
+no cluster touches the edges.  Attachment: hand-built cases with a known
+nearest void (and a tie), plus identities that hold for any input.
+"""
+import numpy as np
+import pytest
+
+from oracle import clusters
+from paper_0802_2488_amd import synth
+
+
+def partition(lab):
+    """Labels -> frozenset of frozensets of pixel indices (label values ignored)."""
+    flat = lab.ravel()
+    groups = {}
+    for i, v in enumerate(flat):
+        if v >= 0:
+            groups.setdefault(int(v), []).append(i)
+    return frozenset(frozenset(g) for g in groups.values())
+
+
+@pytest.mark.parametrize("L,f,seed", [(8, 0.3, 0), (8, 0.6, 1), (16, 0.45, 2), (24, 0.55, 3), (5, 0.5, 4)])
+def test_periodic_labels_equal_breadth_first_search(L, f, seed):
+    phase = synth.bernoulli_mask(L, f, seed).astype(bool)
+    a = clusters.label_periodic(phase)
+    b = clusters.label_bfs(phase)
+    assert np.array_equal(a, b)
+
+
+def test_no_wrap_bonds_matches_scipy_non_periodic():
+    from scipy import ndimage
+    L = 20
+    phase = synth.bernoulli_mask(L, 0.5, 7).astype(bool)
+    phase[0, :] = phase[-1, :] = phase[:, 0] = phase[:, -1] = False
+    lab, n = ndimage.label(phase)
+    ref = np.where(lab > 0, lab, -1)
+    assert partition(clusters.label_periodic(phase)) == partition(ref)
+
+
+def test_wrap_around_bonds_join_clusters():
+    L = 8
+    phase = np.zeros((L, L), bool)
+    phase[3, :2] = True
+    phase[3, -2:] = True          # touches the first two pixels through the x1 edge
+    phase[0, 5] = phase[L - 1, 5] = True   # and through the x2 edge
+    lab = clusters.label_periodic(phase)
+    assert len(np.unique(lab[lab >= 0])) == 2
+    assert lab[3, 0] == lab[3, L - 1] == 3 * L
+    assert lab[0, 5] == lab[L - 1, 5] == 5
+
+
+def test_plastic_cluster_joins_its_nearest_void():
+    L = 12
+    void = np.zeros((L, L), bool)
+    plastic = np.zeros((L, L), bool)
+    void[1, 1] = True                 # index 13
+    void[1, 11] = True                # index 23
+    plastic[6, 0] = plastic[6, 11] = True       # one plastic cluster across the x1 edge
+    plastic[1, 2] = True              # touches void 13
+    lab, st = clusters.analyze(void, plastic)
+    assert st["n_void_clusters"] == 2
+    assert st["n_clusters_raw"] == 3
+    assert st["n_plastic_only_clusters"] == 1
+    assert st["n_isolated_void_clusters"] == 1     # the void at index 23
+    # squared distances: (6, 11) to void 23 is 25; (6, 0) to void 13 is 26
+    assert lab[6, 0] == lab[6, 11] == lab[1, 11] == 23
+    assert st["n_clusters"] == 2 and st["largest"] == 3
+
+
+def test_attachment_tie_goes_to_the_smaller_void_index():
+    L = 9
+    void = np.zeros((L, L), bool)
+    plastic = np.zeros((L, L), bool)
+    void[4, 1] = void[4, 7] = True    # equidistant from (4, 4)
+    plastic[4, 4] = True
+    lab, st = clusters.analyze(void, plastic)
+    assert lab[4, 4] == 4 * L + 1
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_counting_identities_and_symmetries(seed):
+    L = 32
+    void = synth.bernoulli_mask(L, 0.08, seed).astype(bool)
+    plastic = synth.bernoulli_mask(L, 0.25, 100 + seed).astype(bool) & ~void
+    lab, st = clusters.analyze(void, plastic)
+    # plastic-only clusters each merge into exactly one void-holding cluster
+    assert st["n_clusters"] == st["n_clusters_raw"] - st["n_plastic_only_clusters"]
+    assert st["n_void"] + st["n_plastic"] == int((lab >= 0).sum())
+    # every final cluster holds a void
+    for r in np.unique(lab[lab >= 0]):
+        assert void[lab == r].any()
+    # translation and transposition leave every tie-independent count unchanged
+    keys = ("n_void", "n_plastic", "n_void_clusters", "n_clusters_raw", "n_isolated_void_clusters",
+            "n_plastic_only_clusters", "n_clusters")
+    for tv, tp in ((np.roll(void, (3, -5), (0, 1)), np.roll(plastic, (3, -5), (0, 1))), (void.T, plastic.T)):
+        _, s2 = clusters.analyze(tv, tp)
+        assert all(s2[k] == st[k] for k in keys)
+
+
+def test_indicators_of_an_unloaded_grid():
+    L = 32
+    void = synth.bernoulli_mask(L, 0.1, 3).astype(bool)
+    _, st = clusters.analyze(void, np.zeros_like(void))
+    ind = clusters.indicators(st, L)
+    assert ind["i"] == 1.0 and ind["n"] == 1.0
+    f = void.mean()
+    assert ind["f_p"] == pytest.approx(f / (1 - f))
