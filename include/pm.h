@@ -373,6 +373,39 @@ int pm_dg2_combine(const pm_params* params, const uint8_t* d_void_mask, const vo
                    const void* const d_sigma[4], void* d_workspace, size_t workspace_bytes, pm_dg2_out* out,
                    void* stream);
 
+
+/* ------------------------------------------------------------------------
+ * Void and plastic clusters (Sec. 3).  Phases: void (mask 1), plastic
+ * (matrix pixels of a plastic mask, e.g. the output of a step) and elastic.
+ * Clusters are periodic nearest-neighbour (4-connected) components; the
+ * void-plastic phase is the union of voids and plastic pixels, and a plastic
+ * cluster that touches no void is joined to the cluster of its nearest void
+ * pixel (periodic Euclidean distance, ties to the smaller pixel index).
+ * Labels are canonical: a cluster's label is its smallest pixel index
+ * x2 * L + x1; elastic pixels get -1.
+ * ---------------------------------------------------------------------- */
+typedef struct pm_cluster_stats {
+  int64_t n_void, n_plastic;        /* pixels (plastic counts matrix pixels only) */
+  int64_t n_void_clusters;          /* clusters of the void phase alone */
+  int64_t n_clusters_raw;           /* void-plastic clusters before attachment */
+  int64_t n_isolated_void_clusters; /* of those, clusters without plastic pixels */
+  int64_t n_plastic_only_clusters;  /* of those, clusters without voids (attached when voids exist) */
+  int64_t n_clusters;               /* void-plastic clusters after attachment */
+  int64_t largest;                  /* pixels of the largest cluster (ties: smallest label) */
+  int32_t largest_label;            /* its label, -1 if there is no cluster */
+  int32_t spans_x1, spans_x2;       /* the largest cluster holds a pixel in every column / row */
+  int32_t pad;
+} pm_cluster_stats;
+
+/* Device workspace of pm_clusters (about 12 bytes per pixel); 0 if L is invalid. */
+size_t pm_cluster_workspace_bytes(int32_t L);
+
+/* d_void_mask, d_plastic: device L x L uint8 (nonzero = void / plastic).
+ * d_labels: device L x L int32, receives the labels.  Work is queued on
+ * stream; the call synchronises it to return the counts. */
+int pm_clusters(int32_t L, const uint8_t* d_void_mask, const uint8_t* d_plastic, int32_t* d_labels,
+                void* d_workspace, size_t workspace_bytes, pm_cluster_stats* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,16 @@ PM_STEP_CONVERGED, PM_STEP_NOCONV, PM_STEP_NAN = 1, 2, 3
 PM_ADMIT_HOLD = 1
 
 
+class PmClusterStats(ctypes.Structure):
+    _fields_ = [
+        ("n_void", ctypes.c_int64), ("n_plastic", ctypes.c_int64), ("n_void_clusters", ctypes.c_int64),
+        ("n_clusters_raw", ctypes.c_int64), ("n_isolated_void_clusters", ctypes.c_int64),
+        ("n_plastic_only_clusters", ctypes.c_int64), ("n_clusters", ctypes.c_int64), ("largest", ctypes.c_int64),
+        ("largest_label", ctypes.c_int32), ("spans_x1", ctypes.c_int32), ("spans_x2", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+
 class PmDg2Out(ctypes.Structure):
     _fields_ = [
         ("eps", ctypes.c_void_p), ("sigma_of_avg", ctypes.c_void_p), ("sigma_avg", ctypes.c_void_p),
@@ -109,6 +119,10 @@ SIGNATURES = [
     ("pm_batch_fetch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(PmStepOut)]),
     ("pm_batch_release", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("pm_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("pm_cluster_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32]),
+    ("pm_clusters", ctypes.c_int,
+     [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+      ctypes.POINTER(PmClusterStats), ctypes.c_void_p]),
     ("pm_dg2_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(PmParams)]),
     ("pm_dg2_combine", ctypes.c_int,
      [ctypes.POINTER(PmParams), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),

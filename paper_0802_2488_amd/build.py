@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpm.so")
 SOURCES = ["pm_row_f32.hip", "pm_row_f64.hip", "pm_col_f32.hip", "pm_col_f64.hip", "pm_misc.hip", "pm_api.hip",
-           "pm_batch.hip", "pm_dg2.hip"]
+           "pm_batch.hip", "pm_dg2.hip", "pm_cluster.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1,0 +1,50 @@
+"""Void and plastic clusters of a solved grid (Sec. 3) through the C ABI.
+
+``analyze(void_mask, plastic_mask)`` labels the periodic nearest-neighbour
+clusters of the void-plastic phase on the device, joins plastic clusters
+without a void to the cluster of their nearest void, and returns the
+canonical labels with the counts behind the paper's indicators
+(``indicators``).  Argument marshalling only.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import PmClusterStats, check, lib
+
+
+def analyze(void_mask: torch.Tensor, plastic: torch.Tensor, stream=None):
+    """(labels int32 (L, L) on the device, stats dict)."""
+    L = int(void_mask.shape[0])
+    dev = void_mask.device
+    vm = void_mask.to(dtype=torch.uint8).contiguous()
+    pm_ = plastic.to(device=dev, dtype=torch.uint8).contiguous()
+    if tuple(vm.shape) != (L, L) or tuple(pm_.shape) != (L, L):
+        raise ValueError("masks must be L x L")
+    nws = lib().pm_cluster_workspace_bytes(L)
+    if nws == 0:
+        raise ValueError(f"L = {L} must be a power of two in [4, 8192]")
+    ws = torch.empty(nws + 256, dtype=torch.uint8, device=dev)
+    base = ws.data_ptr()
+    ptr = base + (-base) % 256
+    labels = torch.empty((L, L), dtype=torch.int32, device=dev)
+    st = PmClusterStats()
+    s = torch.cuda.current_stream(dev).cuda_stream if stream is None else stream
+    check(lib().pm_clusters(L, vm.data_ptr(), pm_.data_ptr(), labels.data_ptr(), ptr, nws, ctypes.byref(st), s),
+          "pm_clusters")
+    stats = {k: getattr(st, k) for k, _ in st._fields_ if k != "pad"}
+    stats["spans_x1"] = bool(stats["spans_x1"])
+    stats["spans_x2"] = bool(stats["spans_x2"])
+    return labels, stats
+
+
+def indicators(stats, L, f=None):
+    """Sec. 3 indicators: v_p, f_p = v_p / (1 - f), v_max, i and n."""
+    npx = L * L
+    f = stats["n_void"] / npx if f is None else f
+    vp = (stats["n_void"] + stats["n_plastic"]) / npx
+    nvc = max(stats["n_void_clusters"], 1)
+    return dict(v_p=vp, f_p=vp / (1.0 - f), v_max=stats["largest"] / npx,
+                i=stats["n_isolated_void_clusters"] / nvc, n=stats["n_clusters"] / nvc)

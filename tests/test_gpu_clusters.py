@@ -1,0 +1,76 @@
+"""GPU: cluster labels and counts (Sec. 3) through the C ABI, bit-exact
+against the oracle (integer work: labels are canonical, so they compare
+exactly), on random phase maps with plastic-only clusters, on the plastic
+mask of an actual solve, and on the degenerate cases."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import clusters as oc  # noqa: E402
+from paper_0802_2488_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0802_2488_amd import clusters as gc  # noqa: E402
+from paper_0802_2488_amd import solver as pms  # noqa: E402
+
+KEYS = ("n_void", "n_plastic", "n_void_clusters", "n_clusters_raw", "n_isolated_void_clusters",
+        "n_plastic_only_clusters", "n_clusters", "largest", "largest_label", "spans_x1", "spans_x2")
+
+
+def check(void, plastic):
+    lab, st = gc.analyze(torch.tensor(void.astype(np.uint8), device="cuda"),
+                         torch.tensor(plastic.astype(np.uint8), device="cuda"))
+    ref_lab, ref = oc.analyze(void, plastic)
+    assert np.array_equal(lab.cpu().numpy().astype(np.int64), ref_lab)
+    for k in KEYS:
+        assert st[k] == ref[k], k
+    return st
+
+
+@pytest.mark.parametrize("L,fv,fp,seed", [(4, 0.3, 0.3, 0), (8, 0.1, 0.4, 1), (16, 0.05, 0.3, 2), (32, 0.02, 0.35, 3),
+                                          (64, 0.08, 0.45, 4), (128, 0.03, 0.5, 5), (256, 0.1, 0.4, 6),
+                                          (256, 0.01, 0.2, 7)])
+def test_random_phases_bit_exact(L, fv, fp, seed):
+    void = synth.bernoulli_mask(L, fv, seed).astype(bool)
+    plastic = synth.bernoulli_mask(L, fp, 1000 + seed).astype(bool) & ~void
+    st = check(void, plastic)
+    assert st["n_clusters"] == st["n_clusters_raw"] - st["n_plastic_only_clusters"]
+
+
+def test_plastic_mask_of_a_solve():
+    L = 128
+    mask = synth.bernoulli_mask(L, 0.1, 0)
+    s = pms.Solver(torch.tensor(mask, device="cuda"),
+                   pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=1e-6, max_iter=150, precision="fp32"))
+    for E in synth.load_path("equibiaxial", 10, 3.0)[:4]:
+        r = s.step(E)
+        check(mask.astype(bool), r.plastic.cpu().numpy().astype(bool))
+    s.close()
+
+
+@pytest.mark.parametrize("case", ["empty", "all_void", "all_plastic_no_void", "no_void", "one_void"])
+def test_degenerate_cases(case):
+    L = 16
+    void = np.zeros((L, L), bool)
+    plastic = np.zeros((L, L), bool)
+    if case == "all_void":
+        void[:] = True
+    elif case == "all_plastic_no_void":
+        plastic[:] = True
+    elif case == "no_void":
+        plastic = synth.bernoulli_mask(L, 0.4, 3).astype(bool)
+    elif case == "one_void":
+        void[5, 7] = True
+        plastic = synth.bernoulli_mask(L, 0.3, 4).astype(bool) & ~void
+    check(void, plastic)
+
+
+def test_invalid_size():
+    with pytest.raises(ValueError):
+        gc.analyze(torch.zeros((12, 12), dtype=torch.uint8, device="cuda"),
+                   torch.zeros((12, 12), dtype=torch.uint8, device="cuda"))
