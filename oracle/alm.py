@@ -49,7 +49,7 @@ class Params:
     eta_mac: float = 1e-8
     eta_cmp: float = 1e-8
     max_iter: int = 50000
-    green_variant: int = 0    # 0..3: G(q1,q2), G(-q1,-q2), G(-q1,q2), G(q1,-q2)
+    green_variant: int = 0    # 0..3: G(q1,q2), G(-q1,-q2), G(-q1,q2), G(q1,-q2); 4: DG1; 5: CG1
 
     def __post_init__(self):
         if self.mu0 == 0.0:
@@ -121,7 +121,7 @@ class Solver:
         self.void = np.asarray(mask).astype(bool)
         L = p.L
         assert self.void.shape == (L, L)
-        self.G = dg.green_on_grid(L, p.lam0, p.mu0, p.green_variant)
+        self.G = dg.green_variant_on_grid(L, p.lam0, p.mu0, p.green_variant)
         self.lam_mult = None   # Lagrange multiplier lambda (L, L, 3, 3)
         self.eps = None
 

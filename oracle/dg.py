@@ -99,6 +99,41 @@ def green_dg1_on_grid(L: int, lam0: float, mu0: float) -> np.ndarray:
     return (G0 + G1 + sign * (G2 + G3)) / 4.0
 
 
+def frequencies(L: int) -> np.ndarray:
+    """Continuum frequencies of the DFT bins: 2 pi m / L for m < L/2, 2 pi (m - L) / L
+    for m > L/2 (the Nyquist bin m = L/2 is handled by the caller)."""
+    m = np.arange(L)
+    return 2.0 * np.pi * np.where(m < L // 2, m, m - L) / L
+
+
+def green_cg1_on_grid(L: int, lam0: float, mu0: float) -> np.ndarray:
+    """CG1 (Sec. 2): the continuum Green operator, G = -Gamma0(xi), on the half
+    spectrum, with xi the continuum frequencies of the bins.  Modes with a
+    Nyquist component (m1 = L/2 or m2 = L/2) carry no strain (G = 0) and
+    q = 0 is set by the caller; both are readings (the paper only names the
+    method).
+    """
+    xi = frequencies(L)
+    X = np.zeros((L, L // 2 + 1, 2))
+    X[..., 0] = xi[None, : L // 2 + 1]
+    X[..., 1] = xi[:, None]
+    X[0, 0] = (1.0, 0.0)            # placeholder for q = 0, overwritten below
+    G = -continuum_gamma0(X, lam0, mu0)
+    G[0, 0] = 0.0
+    G[:, L // 2] = 0.0
+    G[L // 2, :] = 0.0
+    return G
+
+
+def green_variant_on_grid(L: int, lam0: float, mu0: float, variant: int) -> np.ndarray:
+    """Green tensor of variant 0..3 (sign variants of eq. 3), 4 (DG1) or 5 (CG1)."""
+    if variant == 4:
+        return green_dg1_on_grid(L, lam0, mu0)
+    if variant == 5:
+        return green_cg1_on_grid(L, lam0, mu0)
+    return green_on_grid(L, lam0, mu0, variant)
+
+
 def apply_green(G: np.ndarray, tau_hat: np.ndarray) -> np.ndarray:
     """e_hat_ij = G_ijkl tau_hat_kl on the half spectrum (tau_hat: (..., 2, 2))."""
     return np.einsum("...ijkl,...kl->...ij", G, tau_hat)
@@ -122,3 +157,10 @@ def continuum_gamma0(xi: np.ndarray, lam0: float, mu0: float) -> np.ndarray:
           + np.einsum("hj,...k,...i->...khij", d, xi, xi))
     t2 = np.einsum("...i,...j,...k,...h->...khij", xi, xi, xi, xi)
     return t1 / (4.0 * mu0 * x2) - (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0)) * t2 / x2 ** 2
+
+
+def five_point_average(a: np.ndarray) -> np.ndarray:
+    """CG2 (Sec. 2): the average of a field over each pixel and its four
+    nearest neighbours, periodic; axes 0, 1 are x2, x1."""
+    return (a + np.roll(a, 1, axis=1) + np.roll(a, -1, axis=1) + np.roll(a, 1, axis=0)
+            + np.roll(a, -1, axis=0)) / 5.0

@@ -157,3 +157,63 @@ def test_fourier_divergence_equals_real_space():
     real = np.mean(np.sum(alm.divergence(sig) ** 2, axis=-1))
     four = alm.divergence_fourier(sig)
     assert abs(real - four) < 1e-12 * real
+
+
+def test_cg1_is_the_continuum_projection():
+    """-G of CG1 is the continuum Gamma0 at every non-Nyquist frequency: G C0 G = -G
+    (Gamma0 C0 Gamma0 = Gamma0), real, with major symmetry; Nyquist modes carry nothing."""
+    L = 16
+    G = dg.green_cg1_on_grid(L, LAM0, MU0)
+    C = dg.stiffness_2d(LAM0, MU0)
+    GCG = np.einsum("...ijkl,klmn,...mnpq->...ijpq", G, C, G)
+    sel = np.ones((L, L // 2 + 1), bool)
+    sel[0, 0] = False
+    sel[:, L // 2] = False
+    sel[L // 2, :] = False
+    assert np.abs(GCG[sel] + G[sel]).max() < 1e-14
+    assert not np.iscomplexobj(G) or np.abs(G.imag).max() == 0.0
+    assert np.abs(G - np.transpose(G, (0, 1, 4, 5, 2, 3))).max() < 1e-15
+    assert np.all(G[~sel] == 0.0)
+    # on the long-wavelength modes the discrete tensor of eq. 3 approaches CG1
+    Gd = dg.green_on_grid(L, LAM0, MU0, 0)
+    assert np.abs(Gd[1, 1] - G[1, 1]).max() < 0.2 * np.abs(G[1, 1]).max()
+
+
+def test_dg1_and_cg1_solves_commute_with_the_x1_mirror():
+    """DG1 and CG1 are proper tensors under the lattice mirror, unlike eq. 3:
+    the solve on a mask mirrored in x1 with E12 -> -E12 is the mirrored solve
+    with the 12 components negated, iterate by iterate."""
+    from oracle import alm
+    from paper_0802_2488_amd import synth
+    L = 16
+    mask = synth.bernoulli_mask(L, 0.2, 5)
+    mir = lambda a: a[:, (-np.arange(L)) % L]  # noqa: E731
+    E = (0.3, 0.1, 0.2)
+    for v in (4, 5):
+        a = alm.Solver(mask, alm.Params(L=L, green_variant=v)).step(E, fixed_iters=10)
+        b = alm.Solver(mir(mask), alm.Params(L=L, green_variant=v)).step((E[0], E[1], -E[2]), fixed_iters=10)
+        ref = mir(a.sigma).copy()
+        ref[..., 0, 1] *= -1
+        ref[..., 1, 0] *= -1
+        assert np.abs(b.sigma - ref).max() < 1e-12
+    # the plain tensor of eq. 3 is not mirror symmetric in this sense
+    a = alm.Solver(mask, alm.Params(L=L)).step(E, fixed_iters=10)
+    b = alm.Solver(mir(mask), alm.Params(L=L)).step((E[0], E[1], -E[2]), fixed_iters=10)
+    ref = mir(a.sigma).copy()
+    ref[..., 0, 1] *= -1
+    ref[..., 1, 0] *= -1
+    assert np.abs(b.sigma - ref).max() > 1e-3
+
+
+def test_five_point_average():
+    """CG2's post-processing: each pixel and its four neighbours (periodic)."""
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(8, 8, 2, 2))
+    b = dg.five_point_average(a)
+    y, x = 3, 0
+    ref = (a[y, x] + a[y, 1] + a[y, 7] + a[2, x] + a[4, x]) / 5.0
+    assert np.abs(b[y, x] - ref).max() < 1e-15
+    assert np.abs(b.mean(axis=(0, 1)) - a.mean(axis=(0, 1))).max() < 1e-15   # averages are kept
+    c = np.ones((8, 8))
+    c[::2, ::2] = c[1::2, 1::2] = -1.0      # a checkerboard is damped to 3/5 of its amplitude
+    assert np.abs(dg.five_point_average(c) + 0.6 * c).max() < 1e-15
