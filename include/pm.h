@@ -78,7 +78,14 @@ extern "C" {
  *                    depend on this value.
  *   precision        PM_FP32 or PM_FP64.
  *   green_variant    0: G(q1, q2) of eq. 3; 1: G(-q1, -q2); 2: G(-q1, q2);
- *                    3: G(q1, -q2) (the four tensors of the DG2 scheme).
+ *                    3: G(q1, -q2) (the four tensors of the DG2 scheme);
+ *                    4: DG1, the symmetrised tensor
+ *                    {G(q1,q2) + G(-q1,-q2) + (-1)^(i+j+k+l) [G(-q1,q2) +
+ *                    G(q1,-q2)]} / 4 (Sec. 2); 5: CG1, the continuum
+ *                    operator -Gamma0 at the continuum frequencies of the
+ *                    bins, no strain on modes with a Nyquist component
+ *                    (Sec. 2).  4 and 5 run in the single solver only
+ *                    (pm_batch_admit rejects them).
  */
 typedef struct pm_params {
   int32_t L;
@@ -405,6 +412,14 @@ size_t pm_cluster_workspace_bytes(int32_t L);
  * stream; the call synchronises it to return the counts. */
 int pm_clusters(int32_t L, const uint8_t* d_void_mask, const uint8_t* d_plastic, int32_t* d_labels,
                 void* d_workspace, size_t workspace_bytes, pm_cluster_stats* out, void* stream);
+
+
+/* CG2 (Sec. 2): the average of a field over each pixel and its four nearest
+ * neighbours (periodic), applied plane by plane.  d_in, d_out: device,
+ * nplanes x L x L values of the given precision, not overlapping.  Queued
+ * on stream (not synchronised). */
+int pm_five_point_average(int32_t L, int32_t precision, int32_t nplanes, const void* d_in, void* d_out,
+                          void* stream);
 
 #ifdef __cplusplus
 }

@@ -123,6 +123,8 @@ SIGNATURES = [
     ("pm_clusters", ctypes.c_int,
      [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
       ctypes.POINTER(PmClusterStats), ctypes.c_void_p]),
+    ("pm_five_point_average", ctypes.c_int,
+     [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("pm_dg2_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(PmParams)]),
     ("pm_dg2_combine", ctypes.c_int,
      [ctypes.POINTER(PmParams), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),

@@ -58,7 +58,7 @@ int check_params(const pm_params* p, pm_params* q) {
   if (q->max_iter < 1) return fail(PM_EINVAL, "max_iter must be >= 1");
   if (q->check_every < 0) return fail(PM_EINVAL, "check_every must be >= 0");
   if (q->precision != PM_FP32 && q->precision != PM_FP64) return fail(PM_EINVAL, "precision must be PM_FP32 or PM_FP64");
-  if (q->green_variant < 0 || q->green_variant > 3) return fail(PM_EINVAL, "green_variant must be 0..3");
+  if (q->green_variant < 0 || q->green_variant > 5) return fail(PM_EINVAL, "green_variant must be 0..5");
   return PM_OK;
 }
 
@@ -152,6 +152,10 @@ int upload_tables(pm_solver* s, const uint8_t* mask) {
   return PM_OK;
 }
 
+int green_kind(const pm_params& q) {
+  return q.green_variant == 4 ? pm::GK_DG1 : q.green_variant == 5 ? pm::GK_CG1 : pm::GK_SIGN;
+}
+
 template <typename T>
 int iterate_once(pm_solver* s, int slot_in_chunk) {
   const int L = s->p.L;
@@ -159,7 +163,7 @@ int iterate_once(pm_solver* s, int slot_in_chunk) {
   const pm::Slot<T>* S = dslot<T>(s);
   hipEvent_t* ev = s->timing ? &s->tev[4 * slot_in_chunk] : nullptr;
   if (ev) PM_HIP(hipEventRecord(ev[0], s->stream));
-  PM_HIP(pm::launch_col<T>(L, pm::COL_ALL, S, 1, x, s->stream));
+  PM_HIP(pm::launch_col<T>(L, pm::col_mode(pm::COL_ALL, green_kind(s->p)), S, 1, x, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[1], s->stream));
   PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, S, 1, x, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[2], s->stream));
@@ -328,7 +332,7 @@ int debug_inverse(pm_solver* s, void* d_real) {
 template <typename T>
 int debug_green(pm_solver* s, const double* E) {
   const pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, E);
-  PM_HIP(pm::launch_col<T>(s->p.L, pm::COL_GREEN, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_col<T>(s->p.L, pm::col_mode(pm::COL_GREEN, green_kind(s->p)), dslot<T>(s), 1, x, s->stream));
   PM_HIP(hipStreamSynchronize(s->stream));
   return PM_OK;
 }
@@ -528,6 +532,20 @@ int pm_dg2_combine(const pm_params* params, const uint8_t* d_void_mask, const vo
     out->sigma_avg_mean[c] = means[8 + c];
   }
   out->plastic_fraction = means[12];
+  return PM_OK;
+}
+
+int pm_five_point_average(int32_t L, int32_t precision, int32_t nplanes, const void* d_in, void* d_out,
+                          void* stream) {
+  if (!pmh::is_pow2(L) || L < 4 || L > PM_MAX_L)
+    return fail(PM_EINVAL, "L = %d must be a power of two in [4, %d]", L, PM_MAX_L);
+  if (precision != PM_FP32 && precision != PM_FP64) return fail(PM_EINVAL, "precision must be PM_FP32 or PM_FP64");
+  if (nplanes < 1 || nplanes > 64) return fail(PM_EINVAL, "nplanes = %d must be in [1, 64]", nplanes);
+  if (!d_in || !d_out) return fail(PM_EINVAL, "NULL argument");
+  if (precision == PM_FP64)
+    PM_HIP(pm::launch_avg5<double>(L, nplanes, (const double*)d_in, (double*)d_out, (hipStream_t)stream));
+  else
+    PM_HIP(pm::launch_avg5<float>(L, nplanes, (const float*)d_in, (float*)d_out, (hipStream_t)stream));
   return PM_OK;
 }
 

@@ -368,6 +368,8 @@ int pm_batch_admit(pm_batch* b, const pm_params* params, const uint8_t* d_void_m
   int rc = pmh::check_params(params, &q);
   if (rc != PM_OK) return rc;
   if (!d_void_mask || !E_path) return fail(PM_EINVAL, "mask and E_path must not be NULL");
+  if (q.green_variant > 3) return fail(PM_EINVAL, "green_variant %d (DG1 / CG1) runs in the single solver only",
+                                       q.green_variant);
   if (nsteps < 1) return fail(PM_EINVAL, "nsteps = %d must be >= 1", nsteps);
   for (int n = 0; n < nsteps; ++n) {
     const double* e = E_path + 3 * n;

@@ -107,6 +107,35 @@ hipError_t launch_dg2(int L, const DevParams& prm, const uint8_t* mask, const T*
   return hipGetLastError();
 }
 
+// Five-point periodic average of each plane (CG2 post-processing).
+template <typename T>
+__global__ void __launch_bounds__(256) k_avg5(int L, long nval, const T* __restrict__ in_g, T* __restrict__ out_g) {
+  gptr<const T> in = glb(in_g);
+  gptr<T> out = glb(out_g);
+  const long npx = (long)L * L;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nval; i += (long)gridDim.x * blockDim.x) {
+    const long base = (i / npx) * npx;
+    const long p = i - base;
+    const int x1 = (int)(p % L), x2 = (int)(p / L);
+    const long l = base + (long)x2 * L + (x1 == 0 ? L - 1 : x1 - 1);
+    const long r = base + (long)x2 * L + (x1 + 1 == L ? 0 : x1 + 1);
+    const long u = base + (long)(x2 == 0 ? L - 1 : x2 - 1) * L + x1;
+    const long d = base + (long)(x2 + 1 == L ? 0 : x2 + 1) * L + x1;
+    out[i] = ((((in[i] + in[r]) + in[l]) + in[u]) + in[d]) / (T)5;
+  }
+}
+
+template <typename T>
+hipError_t launch_avg5(int L, int nplanes, const T* in, T* out, hipStream_t s) {
+  const long nval = (long)nplanes * L * L;
+  long g = (nval + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_avg5<T>, dim3((int)g), dim3(256), 0, s, L, nval, in, out);
+  return hipGetLastError();
+}
+template hipError_t launch_avg5<float>(int, int, const float*, float*, hipStream_t);
+template hipError_t launch_avg5<double>(int, int, const double*, double*, hipStream_t);
+
 template hipError_t launch_dg2<float>(int, const DevParams&, const uint8_t*, const float* const*, const float* const*,
                                       float*, float*, float*, uint8_t*, double*, int, hipStream_t);
 template hipError_t launch_dg2<double>(int, const DevParams&, const uint8_t*, const double* const*,

@@ -75,7 +75,7 @@ pm::Slot<T> make_slot(const pm_params& q, char* ws, const Layout& lo, const uint
   S.E_path = nullptr;
   S.rec = nullptr;
   S.prm = dev_params(q);
-  const int v = q.green_variant;
+  const int v = q.green_variant;   // sign variants 0..3; 4 and 5 take no flips
   S.flip1 = (v == 1 || v == 2) ? 1 : 0;
   S.flip2 = (v == 1 || v == 3) ? 1 : 0;
   return S;

@@ -14,6 +14,10 @@ namespace pm {
 
 enum RowMode { ROW_ITER = 0, ROW_INIT = 1, ROW_FWD = 2, ROW_INV = 3, ROW_EMIT = 4 };
 enum ColMode { COL_FWD = 1, COL_GREEN = 2, COL_INV = 4, COL_ALL = 7 };
+// Green tensor of the column pass, in bits 8.. of the column mode: the sign
+// variants of eq. 3 (slot flips), DG1 (symmetrised) or CG1 (continuum).
+enum GreenKind { GK_SIGN = 0, GK_DG1 = 1, GK_CG1 = 2 };
+constexpr int col_mode(int mode, int kind) { return mode | (kind << 8); }
 enum Status { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NOCONV = 2, ST_NAN = 3 };
 
 constexpr int NPART = 8;    // doubles per block in the row-pass partials
@@ -120,6 +124,8 @@ hipError_t launch_dg2(int L, const DevParams& prm, const uint8_t* mask, const T*
                       T* eps_out, T* soa_out, T* sav_out, uint8_t* pl_out, double* partials, int nblk,
                       hipStream_t s);
 int dg2_blocks(int L);
+template <typename T>
+hipError_t launch_avg5(int L, int nplanes, const T* in, T* out, hipStream_t s);
 hipError_t launch_mask(uint8_t* out, long npx, double f, uint64_t seed, hipStream_t s);
 
 }  // namespace pm

@@ -645,9 +645,17 @@ __device__ __forceinline__ void green_apply(cx<T>* tt, cx<T> k1, cx<T> k2, const
 }
 
 // Green tensor at momentum (m1, m2), or E at q = 0.
-template <typename T>
+//   GK_SIGN: eq. 3 at (+-q1, +-q2) (the slot's flips; k(-q) = -conj k(q));
+//   GK_DG1:  the symmetrised tensor {G(q1,q2) + G(-q1,-q2)
+//            + (-1)^(i+j+k+l) [G(-q1,q2) + G(q1,-q2)]} / 4; the sign pattern
+//            is applied as tau12 -> -tau12 before and e12 -> -e12 after;
+//   GK_CG1:  the continuum operator -Gamma0(xi) at the bins' continuum
+//            frequencies (real momenta); modes with a Nyquist component carry
+//            no strain.
+template <int GK, typename T>
 __device__ __forceinline__ void green_at(cx<T>* tt, int m1, int m2, const Slot<T>& S, const Extra<T>& x,
                                          const T lam0, const T mu0, const T scale) {
+  const int L = S.prm.L;
   if (m1 == 0 && m2 == 0) {
     double E0 = x.E[0], E1 = x.E[1], E2 = x.E[2];
     if (x.use_state) {
@@ -659,8 +667,42 @@ __device__ __forceinline__ void green_at(cx<T>* tt, int m1, int m2, const Slot<T
     tt[2] = {(T)E2, (T)0};
     return;
   }
+  if constexpr (GK == GK_CG1) {
+    if (m1 == L / 2 || m2 == L / 2) {
+      tt[0] = tt[1] = tt[2] = {(T)0, (T)0};
+      return;
+    }
+    const double w = 6.283185307179586476925286766559 / (double)L;
+    const cx<T> k1 = {(T)(w * (double)(m1 < L / 2 ? m1 : m1 - L)), (T)0};
+    const cx<T> k2 = {(T)(w * (double)(m2 < L / 2 ? m2 : m2 - L)), (T)0};
+    green_apply(tt, k1, k2, lam0, mu0, scale);
+    return;
+  }
   gptr<const cx<T>> ktab = glb(S.ktab);
   cx<T> k1 = ldc(ktab + m1), k2 = ldc(ktab + m2);
+  if constexpr (GK == GK_DG1) {
+    const cx<T> f1 = {-k1.re, k1.im}, f2 = {-k2.re, k2.im};   // k(-q) = -conj k(q)
+    cx<T> acc[3], u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = tt[c];
+    green_apply(u, k1, k2, lam0, mu0, scale);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = u[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = tt[c];
+    green_apply(u, f1, f2, lam0, mu0, scale);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = acc[c] + u[c];
+    u[0] = tt[0]; u[1] = tt[1]; u[2] = {-tt[2].re, -tt[2].im};
+    green_apply(u, f1, k2, lam0, mu0, scale);
+    acc[0] = acc[0] + u[0]; acc[1] = acc[1] + u[1]; acc[2] = acc[2] - u[2];
+    u[0] = tt[0]; u[1] = tt[1]; u[2] = {-tt[2].re, -tt[2].im};
+    green_apply(u, k1, f2, lam0, mu0, scale);
+    acc[0] = acc[0] + u[0]; acc[1] = acc[1] + u[1]; acc[2] = acc[2] - u[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tt[c] = cscale(acc[c], (T)0.25);
+    return;
+  }
   if (S.flip1) k1 = {-k1.re, k1.im};   // k(-q) = -conj(k(q))
   if (S.flip2) k2 = {-k2.re, k2.im};
   green_apply(tt, k1, k2, lam0, mu0, scale);
@@ -673,9 +715,11 @@ __device__ __forceinline__ void green_at(cx<T>* tt, int m1, int m2, const Slot<T
 // m1 = L/2 (imaginary part): its transform is split with conj-symmetry into
 // the two real-signal spectra, each gets its own Green tensor, and the
 // results are packed again before the inverse.
-template <typename T, int L, int RMAX, int W, int CB, int MODE>
+template <typename T, int L, int RMAX, int W, int CB, int MODE_GK>
 __global__ void __launch_bounds__(CB*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_COL_WPE)))
 k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
+  constexpr int MODE = MODE_GK & 0xff;
+  constexpr int GK = MODE_GK >> 8;
   static_assert(W % CB == 0, "columns per block must divide the tile width");
   constexpr int TPF = L / RMAX;
   constexpr int LS = LdsSize<L>::value;
@@ -734,8 +778,8 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
             x0[c] = cscale(v[c][s] + zr, (T)0.5);
             xn[c] = {d.im * (T)0.5, -d.re * (T)0.5};
           }
-          green_at(x0, 0, m2, S, x, lam0, mu0, scale);
-          green_at(xn, L / 2, m2, S, x, lam0, mu0, scale);
+          green_at<GK>(x0, 0, m2, S, x, lam0, mu0, scale);
+          green_at<GK>(xn, L / 2, m2, S, x, lam0, mu0, scale);
 #pragma unroll
           for (int c = 0; c < 3; ++c) v[c][s] = {x0[c].re - xn[c].im, x0[c].im + xn[c].re};
         }
@@ -746,7 +790,7 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
       for (int s = 0; s < RMAX; ++s) {
         const int m2 = t + TPF * s;
         cx<T> tt[3] = {v[0][s], v[1][s], v[2][s]};
-        green_at(tt, m1, m2, S, x, lam0, mu0, scale);
+        green_at<GK>(tt, m1, m2, S, x, lam0, mu0, scale);
         v[0][s] = tt[0]; v[1][s] = tt[1]; v[2][s] = tt[2];
       }
     }
@@ -850,6 +894,10 @@ static hipError_t launch_col_L(int mode, const Slot<T>* slots, int nslots, const
     case COL_FWD: return launch_col_LM<T, L, COL_FWD>(slots, nslots, x, st);
     case COL_INV: return launch_col_LM<T, L, COL_INV>(slots, nslots, x, st);
     case COL_GREEN: return launch_col_LM<T, L, COL_GREEN>(slots, nslots, x, st);
+    case col_mode(COL_ALL, GK_DG1): return launch_col_LM<T, L, col_mode(COL_ALL, GK_DG1)>(slots, nslots, x, st);
+    case col_mode(COL_ALL, GK_CG1): return launch_col_LM<T, L, col_mode(COL_ALL, GK_CG1)>(slots, nslots, x, st);
+    case col_mode(COL_GREEN, GK_DG1): return launch_col_LM<T, L, col_mode(COL_GREEN, GK_DG1)>(slots, nslots, x, st);
+    case col_mode(COL_GREEN, GK_CG1): return launch_col_LM<T, L, col_mode(COL_GREEN, GK_CG1)>(slots, nslots, x, st);
     default: return hipErrorInvalidValue;
   }
 }

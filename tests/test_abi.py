@@ -35,11 +35,11 @@ def test_workspace_bytes_and_validation():
     n64 = L.pm_workspace_bytes(ctypes.byref(p))
     p32 = make_params(64, precision="fp32")
     n32 = L.pm_workspace_bytes(ctypes.byref(p32))
-    # strain state (4 planes) and 3-component half spectrum dominate
+    # stress state (4 planes) and 3-component half spectrum dominate
     assert n64 > 4 * 64 * 64 * 8 + 64 * 33 * 48
     assert n32 < n64
     for bad in (make_params(48), make_params(2), make_params(16384), make_params(64, mu=-1.0),
-                make_params(64, Y=0.0), make_params(64, max_iter=0), make_params(64, green_variant=4),
+                make_params(64, Y=0.0), make_params(64, max_iter=0), make_params(64, green_variant=6),
                 make_params(64, mu0=-1.0)):
         assert L.pm_workspace_bytes(ctypes.byref(bad)) == 0
         assert b"" != L.pm_last_error()

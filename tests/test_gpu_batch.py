@@ -191,6 +191,11 @@ def test_batch_invalid_arguments():
         b.records(s, 0, 1)                             # nothing finished yet
     with pytest.raises(PmError):
         b.tick(0)
+    for v in (4, 5):                                   # DG1 / CG1 run in the single solver
+        q = params(L, "fp32")
+        q.green_variant = v
+        with pytest.raises(PmError):
+            b.admit(mask, q, [(0.1, 0.1, 0.0)])
     b.close()
     with pytest.raises(PmError):
         pmb.Batch(1024, max_slots=4)                   # smaller than the fixed part

@@ -114,7 +114,7 @@ def test_fft_inverse_matches_numpy(L, precision, tol):
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("L", [8, 64, 512])
 def test_green_kernel_matches_oracle(L, variant):
     s = _solver(L, "fp64", variant=variant)
@@ -129,7 +129,7 @@ def test_green_kernel_matches_oracle(L, variant):
     s.debug_green(E)
     a = spec.cpu().numpy().reshape(L // 2 // WT, L, WT, 3, 2)
     got = (a[..., 0] + 1j * a[..., 1]).transpose(1, 0, 2, 3).reshape(L, L // 2, 3)
-    G = dg.green_on_grid(L, 4.0, 2.0, variant)
+    G = dg.green_variant_on_grid(L, 4.0, 2.0, variant)
 
     def apply(Gq, v):
         tau = np.empty(v.shape[:-1] + (2, 2), complex)
@@ -184,7 +184,7 @@ def test_iteration_locked_fp64(L, f, seed, iters):
         assert abs(rg.res_eq - ro.res_eq) <= 1e-8 * ro.res_eq
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 def test_iteration_locked_green_variants(variant):
     _, out = _run_locked(32, 0.2, 4, [(0.4, 0.2, 0.1)], 12, "fp64", variant=variant)
     rg, ro = out[0]
@@ -287,3 +287,35 @@ def test_invalid_arguments():
     from paper_0802_2488_amd._lib import PmError
     with pytest.raises(PmError):
         pms.Solver(torch.zeros((48, 48), dtype=torch.uint8, device="cuda"), gpu_params(48, "fp32"))
+
+
+@pytest.mark.parametrize("variant", [4, 5])
+def test_dg1_and_cg1_commute_with_the_x1_mirror(variant):
+    """DG1 and CG1 transform as proper tensors under the x1 mirror (E12 and the
+    12 components change sign); checked on the GPU to rounding."""
+    L = 64
+    mask = synth.bernoulli_mask(L, 0.2, 6)
+    mir = mask[:, (-np.arange(L)) % L]
+    E = (0.3, 0.1, 0.2)
+    p = gpu_params(L, "fp64", tol=0.0, max_iter=15, variant=variant)
+    a = pms.Solver(torch.tensor(mask, device="cuda"), p).step(E)
+    b = pms.Solver(torch.tensor(mir, device="cuda"), p).step((E[0], E[1], -E[2]))
+    ref = a.sigma.cpu().numpy()[:, :, (-np.arange(L)) % L].copy()
+    ref[3] *= -1.0
+    assert np.abs(b.sigma.cpu().numpy() - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("L,precision,tol", [(16, "fp64", 1e-15), (1024, "fp32", 1e-6)])
+def test_five_point_average_matches_oracle(L, precision, tol):
+    from paper_0802_2488_amd import _lib
+    rng = np.random.default_rng(L)
+    x = rng.normal(size=(4, L, L))
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    xin = torch.tensor(x, dtype=dt, device="cuda")
+    out = torch.empty_like(xin)
+    prec = _lib.PM_FP64 if precision == "fp64" else _lib.PM_FP32
+    _lib.check(_lib.lib().pm_five_point_average(L, prec, 4, xin.data_ptr(), out.data_ptr(),
+                                                torch.cuda.current_stream().cuda_stream), "pm_five_point_average")
+    torch.cuda.synchronize()
+    ref = np.moveaxis(dg.five_point_average(np.moveaxis(xin.cpu().double().numpy(), 0, -1)), -1, 0)
+    assert np.abs(out.cpu().double().numpy() - ref).max() <= tol * np.abs(ref).max()
