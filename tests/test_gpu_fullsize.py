@@ -1,0 +1,89 @@
+"""GPU parity at the workload sizes, in the launch configuration the benchmark
+times (FP32 fields, FP64 norms, default kernels).
+
+L = 1024 (the curve-and-masks workload) and L = 4096 (the benchmark
+workload) are compared with the FP64 oracle iteration-locked over a few
+iterations of their first load steps.  At L = 8192, the largest size the
+library accepts, the checks are properties that hold at any size: exact
+uniform fields in a homogeneous medium, zero stress in voids and the Mises
+cap, and FP32 against the library's own FP64 path (which the smaller-size
+tests pin to the oracle).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import alm, hencky  # noqa: E402
+from paper_0802_2488_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0802_2488_amd import solver as pms  # noqa: E402
+
+
+def t33(planes):
+    return alm.from_voigt4(np.moveaxis(planes.detach().cpu().double().numpy(), 0, -1))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def params(L, precision, max_iter, tol=0.0):
+    return pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=tol, max_iter=max_iter, precision=precision)
+
+
+@pytest.mark.parametrize("L,f,kind,steps,iters", [(1024, 0.2, "equibiaxial", 2, 4), (4096, 0.3, "shear", 1, 2)])
+def test_workload_sizes_iteration_locked_fp32(L, f, kind, steps, iters):
+    mask = synth.bernoulli_mask(L, f, 0)
+    nsteps = 50 if L == 1024 else 40
+    path = synth.load_path(kind, nsteps, synth.default_emax(kind, 1.0, 1.0))[:steps]
+    g = pms.Solver(torch.tensor(mask, device="cuda"), params(L, "fp32", iters))
+    o = alm.Solver(mask, alm.Params(L=L))
+    for E in path:
+        rg = g.step(E)
+        ro = o.step(E, fixed_iters=iters)
+        assert rg.iters == iters
+        assert rel(t33(rg.sigma), ro.sigma) <= 1e-4
+        band = np.abs(ro.margin) <= 1e-5
+        assert np.array_equal(rg.plastic.cpu().numpy().astype(bool)[~band], ro.plastic[~band])
+        np.testing.assert_allclose(rg.sigma_mean, alm.voigt4(ro.sigma_mean), rtol=1e-4, atol=1e-6)
+        del ro
+    g.close()
+
+
+def test_max_size_homogeneous_medium_exact():
+    L = 8192
+    g = pms.Solver(torch.zeros((L, L), dtype=torch.uint8, device="cuda"), params(L, "fp32", 50, tol=1e-6))
+    E = (0.7, 0.2, 0.1)
+    r = g.step(E)
+    assert r.converged and r.iters == 2
+    ref = alm.voigt4(hencky.stress(alm.tensor_from_voigt(E), 1.0, 2.0, 1.0))
+    s = r.sigma
+    for c in range(4):
+        assert float((s[c] - ref[c]).abs().max()) <= 1e-6 * np.abs(ref).max()
+    g.close()
+
+
+def test_max_size_porous_fp32_against_fp64_and_invariants():
+    L = 8192
+    mask = synth.bernoulli_mask(L, 0.3, 1)
+    tm = torch.tensor(mask, device="cuda")
+    E = (0.0, 0.0, 0.1)
+    r32 = pms.Solver(tm, params(L, "fp32", 4)).step(E)
+    s32 = r32.sigma.double()
+    del r32
+    r64 = pms.Solver(tm, params(L, "fp64", 4)).step(E)
+    s64 = r64.sigma
+    assert float(torch.linalg.vector_norm(s32 - s64) / torch.linalg.vector_norm(s64)) <= 1e-4
+    void = tm.bool()
+    assert float(s64[:, void].abs().max()) == 0.0
+    # Mises norm of the stress deviator never exceeds the yield stress
+    tr = (s64[0] + s64[1] + s64[2]) / 3.0
+    d2 = (s64[0] - tr) ** 2 + (s64[1] - tr) ** 2 + (s64[2] - tr) ** 2 + 2.0 * s64[3] ** 2
+    assert float(torch.sqrt(1.5 * d2).max()) <= 1.0 + 1e-12
+    assert not bool(r64.plastic[void].any())
