@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (reference for HBM byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-realization workload")
+    ap.add_argument("--no-next", action="store_true", help="skip the DG2 / cluster / method measurements")
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--batch-max-iter", type=int, default=500)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
@@ -139,6 +140,7 @@ def run_gpu(L, precision, steps, warmup, max_iter, timing=True):
     tm = s.timing(False) if timing else None
     s.close()
     iters = sum(r.iters for r in recs)
+    last_plastic = recs[-1].plastic
     info = dict(
         iters_per_step=[r.iters for r in recs],
         converged=[r.converged for r in recs],
@@ -148,7 +150,7 @@ def run_gpu(L, precision, steps, warmup, max_iter, timing=True):
         sigma12_mean=[float(r.sigma_mean[3]) for r in recs],
         plastic_fraction=[float(r.plastic.float().mean()) for r in recs],
     )
-    return dict(value=L * L * iters / dt, seconds=dt, iters=iters, info=info, timing=tm)
+    return dict(value=L * L * iters / dt, seconds=dt, iters=iters, info=info, timing=tm, last_plastic=last_plastic)
 
 
 def batch_jobs(n, max_iter):
@@ -251,6 +253,98 @@ def serving_section(a):
     }
 
 
+def precision_check(L, iters=100):
+    """Relative L2 difference of the FP32 and FP64 stress after the same
+    iterations of load step 1 (the FP64 path is pinned to the oracle)."""
+    import torch
+
+    from paper_0802_2488_amd import solver as pms
+    from paper_0802_2488_amd import synth
+
+    mask = pms.device_mask(L, 0.3, 0)
+    E = synth.load_path("shear", 40, synth.default_emax("shear", 1.0, 1.0))[0]
+    out = {}
+    for prec in ("fp32", "fp64"):
+        s = pms.Solver(mask, pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=0.0, max_iter=iters, precision=prec))
+        out[prec] = s.step(E).sigma.double()
+        s.close()
+    d = float(torch.linalg.vector_norm(out["fp32"] - out["fp64"]) / torch.linalg.vector_norm(out["fp64"]))
+    return {"what": f"load step 1, {iters} iterations at L={L}", "rel_l2_stress_fp32_vs_fp64": d}
+
+
+def next_rows_section(plastic_4096=None):
+    """Measurements of the extension rows: DG2, plastic clusters, DG1 / CG1."""
+    import torch
+
+    from paper_0802_2488_amd import clusters, dg2
+    from paper_0802_2488_amd import solver as pms
+    from paper_0802_2488_amd import synth
+
+    out = {}
+    # DG2: four Green-tensor variants in one batch, combined after every load step
+    L = 1024
+    mask = pms.device_mask(L, 0.2, 0)
+    p = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=1e-6, max_iter=200, precision="fp32")
+    path = synth.load_path("equibiaxial", 50, 3.0)[:3]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = dg2.solve_path(mask, p, path)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(r.iters for st in steps for r in st.records)
+    eps4 = [torch.randn((4, L, L), device="cuda") for _ in range(4)]
+    sig4 = [torch.randn((4, L, L), device="cuda") for _ in range(4)]
+    dg2.combine(p, mask, eps4, sig4)
+    torch.cuda.synchronize()
+    reps = 20
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        dg2.combine(p, mask, eps4, sig4)
+    torch.cuda.synchronize()
+    tc = (time.perf_counter() - t1) / reps
+    cb = L * L * (4 * 16 + 4 * 16 + 1 + 3 * 16 + 1)
+    out["dg2"] = {"workload": f"L={L}, f=0.2, equibiaxial load steps 1-3 of 50, tol 1e-6, FP32, max_iter 200, "
+                              "four variants in one batch",
+                  "pixel_iters_per_s": L * L * iters / dt, "seconds": dt, "iters_per_variant_step":
+                  [[r.iters for r in st.records] for st in steps],
+                  "sigma_of_avg_mean_last": [float(v) for v in steps[-1].sigma_of_avg_mean],
+                  "combine_ms": 1e3 * tc, "combine_GBs": cb / tc / 1e9,
+                  "combine_bytes_per_call": cb}
+    print(f"# dg2 done: {out['dg2']['pixel_iters_per_s']:.3e} px-iter/s", file=sys.stderr, flush=True)
+    # plastic clusters of the benchmark's last load step
+    if plastic_4096 is not None:
+        L = 4096
+        vm = pms.device_mask(L, 0.3, 0)
+        clusters.analyze(vm, plastic_4096)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            lab, st = clusters.analyze(vm, plastic_4096)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        tm = sorted(times)[len(times) // 2]
+        out["clusters"] = {"workload": "L=4096 void mask f=0.3 with the plastic mask of the benchmark's last "
+                                       "timed load step", "ms": 1e3 * tm, "pixels_per_s": L * L / tm,
+                           "stats": st, "indicators": clusters.indicators(st, L)}
+        print(f"# clusters done: {1e3 * tm:.2f} ms", file=sys.stderr, flush=True)
+    # iterations to a tolerance with the tensor of eq. 3, DG1 and CG1 (Sec. 2 compares the methods)
+    L = 128
+    m = pms.device_mask(L, 0.1, 0)
+    its = {}
+    for name, v in (("eq3", 0), ("DG1", 4), ("CG1", 5)):
+        q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.5, lam0=1.0, tol=1e-5, max_iter=4000,
+                            precision="fp64", green_variant=v)
+        s = pms.Solver(m, q)
+        r = s.step(synth.load_path("equibiaxial", 10, 3.0)[0], fields=False)
+        its[name] = {"iters": r.iters, "converged": r.converged, "res_eq": r.res_eq, "res_mac": r.res_mac,
+                     "res_cmp": r.res_cmp}
+        s.close()
+    out["method_iterations"] = {"workload": f"L={L}, f=0.1, equibiaxial load step 1 of 10, reference medium "
+                                            "0.5x matrix, tol 1e-5, FP64, max_iter 4000", **its}
+    return out
+
+
 def cpu_baseline(L):
     """The FP64 oracle on this host: one iteration of the first load step."""
     import numpy as np
@@ -299,6 +393,9 @@ def main():
     if not a.no_fp64:
         r64 = run_gpu(L, "fp64", min(a.steps, 2), 1, min(a.max_iter, 200))
         print(f"# fp64 done: {r64['value']:.4e} px-iter/s", file=sys.stderr, flush=True)
+    prec = precision_check(L) if not a.no_fp64 else None
+    nxt = None if a.no_next else next_rows_section(r32.get("last_plastic"))
+    r32.pop("last_plastic", None)
     batched = None if a.no_batch else batched_section(a)
     serving = None if a.no_serve else serving_section(a)
     cpu = None if a.no_cpu else cpu_baseline(L)
@@ -334,7 +431,9 @@ def main():
         },
         "iterations": r32["info"],
         "fp64": None if r64 is None else {"value": r64["value"], "unit": "pixel-iters/s",
-                                          "iters_per_step": r64["info"]["iters_per_step"]},
+                                          "iters_per_step": r64["info"]["iters_per_step"],
+                                          "precision_check": prec},
+        "next_rows": nxt,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,
