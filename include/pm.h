@@ -347,6 +347,13 @@ int pm_batch_fetch(pm_batch* batch, int32_t slot, pm_step_out* out);
 int pm_batch_release(pm_batch* batch, int32_t slot);
 int pm_batch_destroy(pm_batch* batch);
 
+/* enable = 1 (the default): once a slot table has run one tick eagerly, the
+ * launches of later ticks with that table and iteration count are captured
+ * into a HIP graph and replayed; 0 launches every tick eagerly.  Results do
+ * not depend on it.  The engine works on a stream of its own (default
+ * priority), ordered after the caller's stream at every call. */
+int pm_batch_set_graphs(pm_batch* batch, int32_t enable);
+
 
 /* ------------------------------------------------------------------------
  * DG2 (Sec. 2, "Discrete Green functions"): the same system is solved to

@@ -119,6 +119,7 @@ SIGNATURES = [
     ("pm_batch_fetch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(PmStepOut)]),
     ("pm_batch_release", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("pm_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("pm_batch_set_graphs", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("pm_cluster_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32]),
     ("pm_clusters", ctypes.c_int,
      [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,

@@ -124,6 +124,10 @@ class Batch:
         check(lib().pm_batch_fetch(self.handle, slot, ctypes.byref(out)), "pm_batch_fetch")
         return sig, eps, pl, out
 
+    def set_graphs(self, enable: bool):
+        """Replay each tick as a HIP graph once its slot table ran eagerly (default on)."""
+        check(lib().pm_batch_set_graphs(self.handle, 1 if enable else 0), "pm_batch_set_graphs")
+
     def resume(self, slot: int):
         check(lib().pm_batch_resume(self.handle, slot), "pm_batch_resume")
 

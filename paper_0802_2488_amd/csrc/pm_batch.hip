@@ -144,7 +144,9 @@ struct pm_batch {
   char* pool;
   size_t pool_bytes;
   int max_slots;
-  hipStream_t stream;
+  hipStream_t user;          // the caller's stream
+  hipStream_t stream;        // the engine's own stream (default priority), capturable
+  hipEvent_t ev_user;        // orders the engine's work after the caller's
   int device;
   Fixed fx;
   RangeAlloc heap;
@@ -157,6 +159,13 @@ struct pm_batch {
   DevState* hstates;         // pinned readback of the slot states
   hipEvent_t stage_done;
   int hi;                    // 1 + highest slot id in use
+  // a tick's launches are captured into a graph once the table has run eagerly
+  bool use_graph;
+  uint64_t table_version;    // bumped by every table upload
+  uint64_t eager_version;    // table version of the last eager tick
+  uint64_t graph_version;    // table version and iteration count the graph holds
+  int graph_iters;
+  hipGraphExec_t gexec;
 };
 
 namespace {
@@ -215,6 +224,7 @@ int rebuild_table(pm_batch* b) {
     PM_HIP(hipMemcpyAsync(b->pool + b->fx.table, b->stage, (size_t)n * SLOT_DESC, hipMemcpyHostToDevice, b->stream));
   PM_HIP(hipEventRecord(b->stage_done, b->stream));
   b->dirty = false;
+  ++b->table_version;
   return PM_OK;
 }
 
@@ -239,6 +249,63 @@ int finish_group(pm_batch* b, int g) {
   PM_HIP(pm::launch_row<T>(L, pm::ROW_EMIT, tab, n, x, b->stream));
   PM_HIP(pm::launch_reduce_emit<T>(tab, n, pm::row_blocks<T>(L), pm::GATE_PENDING, b->stream));
   PM_HIP(pm::launch_advance<T>(tab, n, b->stream));
+  return PM_OK;
+}
+
+// Order the engine's stream after the work already queued on the caller's.
+int sync_in(pm_batch* b) {
+  PM_HIP(hipEventRecord(b->ev_user, b->user));
+  PM_HIP(hipStreamWaitEvent(b->stream, b->ev_user, 0));
+  return PM_OK;
+}
+
+// All launches of one tick: iters iterations of every group, then the end of
+// the load steps that finished.
+int tick_launches(pm_batch* b, int iters) {
+  for (int it = 0; it < iters; ++it) {
+    for (int g = 0; g < NGROUP; ++g) {
+      if (!b->grp_count[g]) continue;
+      int rc = group_fp64(g) ? iterate_group<double>(b, g) : iterate_group<float>(b, g);
+      if (rc != PM_OK) return rc;
+    }
+  }
+  for (int g = 0; g < NGROUP; ++g) {
+    if (!b->grp_count[g]) continue;
+    int rc = group_fp64(g) ? finish_group<double>(b, g) : finish_group<float>(b, g);
+    if (rc != PM_OK) return rc;
+  }
+  return PM_OK;
+}
+
+int drop_graph(pm_batch* b) {
+  if (b->gexec) {
+    PM_HIP(hipGraphExecDestroy(b->gexec));
+    b->gexec = nullptr;
+  }
+  return PM_OK;
+}
+
+// Capture the tick's launches on the engine's stream and instantiate them.
+int capture_tick(pm_batch* b, int iters) {
+  int rc = drop_graph(b);
+  if (rc != PM_OK) return rc;
+  PM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  rc = tick_launches(b, iters);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+  if (rc != PM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(PM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  const hipError_t ei = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    b->gexec = nullptr;
+    return fail(PM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  }
+  b->graph_version = b->table_version;
+  b->graph_iters = iters;
   return PM_OK;
 }
 
@@ -330,7 +397,7 @@ int pm_batch_create(pm_batch** out, void* d_pool, size_t pool_bytes, int32_t max
   b->pool = (char*)d_pool;
   b->pool_bytes = pool_bytes;
   b->max_slots = max_slots;
-  b->stream = (hipStream_t)stream;
+  b->user = (hipStream_t)stream;
   b->fx = fx;
   b->heap.reset(fx.total, pool_bytes / 256 * 256);
   b->slots.resize(max_slots);
@@ -340,14 +407,26 @@ int pm_batch_create(pm_batch** out, void* d_pool, size_t pool_bytes, int32_t max
   }
   b->dirty = true;
   b->hi = 0;
+  b->use_graph = true;
+  b->table_version = 1;
+  b->eager_version = 0;
+  b->graph_version = 0;
+  b->graph_iters = 0;
+  b->gexec = nullptr;
   auto cleanup = [&](int code) {
     if (b->stage) (void)hipHostFree(b->stage);
     if (b->hstates) (void)hipHostFree(b->hstates);
     if (b->stage_done) (void)hipEventDestroy(b->stage_done);
+    if (b->ev_user) (void)hipEventDestroy(b->ev_user);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return code;
   };
   if (hipGetDevice(&b->device) != hipSuccess) return cleanup(fail(PM_EDEVICE, "hipGetDevice failed"));
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(fail(PM_EDEVICE, "hipStreamCreate failed"));
+  if (hipEventCreateWithFlags(&b->ev_user, hipEventDisableTiming) != hipSuccess)
+    return cleanup(fail(PM_EDEVICE, "hipEventCreate failed"));
   if (hipHostMalloc((void**)&b->stage, (size_t)max_slots * SLOT_DESC, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&b->hstates, (size_t)max_slots * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(PM_EDEVICE, "pinned host allocation failed"));
@@ -388,6 +467,11 @@ int pm_batch_admit(pm_batch* b, const pm_params* params, const uint8_t* d_void_m
   if (!b->heap.take(sl.total, &off))
     return fail(PM_EBUSY, "no free pool range of %zu bytes (largest free %zu)", sl.total, b->heap.largest());
   const int g = group_of(q.precision, q.L);
+  rc = sync_in(b);
+  if (rc != PM_OK) {
+    b->heap.give(off, sl.total);
+    return rc;
+  }
   rc = upload_group_tables(b, g);
   if (rc != PM_OK) {
     b->heap.give(off, sl.total);
@@ -422,19 +506,21 @@ int pm_batch_tick(pm_batch* b, int32_t iters, int32_t* running) {
   if (!b) return fail(PM_EINVAL, "batch is NULL");
   if (iters < 1) return fail(PM_EINVAL, "iters = %d must be >= 1", iters);
   if (hipSetDevice(b->device) != hipSuccess) return fail(PM_EDEVICE, "hipSetDevice failed");
-  int rc = rebuild_table(b);
+  int rc = sync_in(b);
   if (rc != PM_OK) return rc;
-  for (int it = 0; it < iters; ++it) {
-    for (int g = 0; g < NGROUP; ++g) {
-      if (!b->grp_count[g]) continue;
-      rc = group_fp64(g) ? iterate_group<double>(b, g) : iterate_group<float>(b, g);
+  rc = rebuild_table(b);
+  if (rc != PM_OK) return rc;
+  if (b->use_graph && b->eager_version == b->table_version) {
+    // the table ran eagerly once (kernel attributes set): replay a graph
+    if (!b->gexec || b->graph_version != b->table_version || b->graph_iters != iters) {
+      rc = capture_tick(b, iters);
       if (rc != PM_OK) return rc;
     }
-  }
-  for (int g = 0; g < NGROUP; ++g) {
-    if (!b->grp_count[g]) continue;
-    rc = group_fp64(g) ? finish_group<double>(b, g) : finish_group<float>(b, g);
+    PM_HIP(hipGraphLaunch(b->gexec, b->stream));
+  } else {
+    rc = tick_launches(b, iters);
     if (rc != PM_OK) return rc;
+    b->eager_version = b->table_version;
   }
   if (b->hi > 0)
     PM_HIP(hipMemcpyAsync(b->hstates, b->pool + b->fx.states, (size_t)b->hi * sizeof(DevState),
@@ -481,6 +567,8 @@ int pm_batch_resume(pm_batch* b, int32_t slot) {
   if (h.finished || !h.st.held) return fail(PM_EINVAL, "slot %d is not waiting after a load step", slot);
   const int next = h.st.step + 1;
   if (hipSetDevice(b->device) != hipSuccess) return fail(PM_EDEVICE, "hipSetDevice failed");
+  rc = sync_in(b);
+  if (rc != PM_OK) return rc;
   PM_HIP(pm::launch_begin(dev_state(b, slot), h.E.data() + 3 * (size_t)next, h.q.mu, next, h.nsteps, h.hold,
                           b->stream));
   h.st.held = 0;
@@ -507,6 +595,8 @@ int pm_batch_fetch(pm_batch* b, int32_t slot, pm_step_out* out) {
   if (rc != PM_OK) return rc;
   if (!out) return fail(PM_EINVAL, "out is NULL");
   if (hipSetDevice(b->device) != hipSuccess) return fail(PM_EDEVICE, "hipSetDevice failed");
+  rc = sync_in(b);
+  if (rc != PM_OK) return rc;
   return b->slots[slot].q.precision == PM_FP64 ? fetch_impl<double>(b, slot, out) : fetch_impl<float>(b, slot, out);
 }
 
@@ -529,9 +619,19 @@ int pm_batch_release(pm_batch* b, int32_t slot) {
   return PM_OK;
 }
 
+int pm_batch_set_graphs(pm_batch* b, int32_t enable) {
+  if (!b) return fail(PM_EINVAL, "batch is NULL");
+  b->use_graph = enable != 0;
+  if (!b->use_graph) return drop_graph(b);
+  return PM_OK;
+}
+
 int pm_batch_destroy(pm_batch* b) {
   if (!b) return PM_OK;
   (void)hipStreamSynchronize(b->stream);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->ev_user) (void)hipEventDestroy(b->ev_user);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
   if (b->stage) (void)hipHostFree(b->stage);
   if (b->hstates) (void)hipHostFree(b->hstates);
   if (b->stage_done) (void)hipEventDestroy(b->stage_done);

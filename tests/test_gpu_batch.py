@@ -103,6 +103,23 @@ def test_batch_bitwise_equals_single_solver(tick_iters):
     assert saw == {1, 2}
 
 
+def test_graph_replays_match_eager_ticks():
+    """Ticks replayed from a captured graph give the same records as eager
+    ticks; admissions and releases between replays force recaptures."""
+    jobs = mixed_jobs()
+    out = []
+    for graphs in (False, True):
+        b = pmb.Batch(pool_for(jobs, 3), max_slots=3)      # fewer slots than jobs: slots turn over
+        b.set_graphs(graphs)
+        out.append(pmb.run_all(b, jobs, tick_iters=5))
+        b.close()
+    for ra, rb in zip(*out):
+        assert len(ra) == len(rb)
+        for x, y in zip(ra, rb):
+            assert x.iters == y.iters and x.status == y.status
+            assert np.array_equal(x.sigma_mean, y.sigma_mean) and np.array_equal(x.eps_mean, y.eps_mean)
+
+
 def test_batch_fp64_slot_matches_oracle_iteration_locked():
     L, iters = 32, 9
     mask = synth.bernoulli_mask(L, 0.2, 7)
