@@ -428,6 +428,31 @@ int pm_clusters(int32_t L, const uint8_t* d_void_mask, const uint8_t* d_plastic,
 int pm_five_point_average(int32_t L, int32_t precision, int32_t nplanes, const void* d_in, void* d_out,
                           void* stream);
 
+
+/* ------------------------------------------------------------------------
+ * Autotuning.  For each (precision, L) the iteration kernels exist in two
+ * variants: the row pass with another FFT radix, and the column pass with
+ * another radix (and columns per block).  The data layout is the same for
+ * all variants.  The choice is process-wide and read at every iteration by
+ * solvers and batches; results of a solve depend on it only through
+ * rounding.  Change it between solves, not during them.
+ * ---------------------------------------------------------------------- */
+typedef struct pm_tune_result {
+  int32_t row_variant, col_variant;    /* the fastest, now in effect */
+  double ms_per_iteration[2][2];       /* measured [row][col] */
+} pm_tune_result;
+
+/* Device workspace pm_autotune needs (a solver's workspace and a mask). */
+size_t pm_autotune_workspace_bytes(int32_t L, int32_t precision);
+
+/* Time iters iterations of every variant pair on a synthetic grid (voids
+ * f = 0.2, material mu = 1, lambda = 2, Y = 1) and put the fastest into
+ * effect for (L, precision).  Blocking. */
+int pm_autotune(int32_t L, int32_t precision, int32_t iters, void* d_workspace, size_t workspace_bytes,
+                void* stream, pm_tune_result* out);
+int pm_set_tuning(int32_t L, int32_t precision, int32_t row_variant, int32_t col_variant);
+int pm_get_tuning(int32_t L, int32_t precision, int32_t* row_variant, int32_t* col_variant);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,11 @@ PM_STEP_CONVERGED, PM_STEP_NOCONV, PM_STEP_NAN = 1, 2, 3
 PM_ADMIT_HOLD = 1
 
 
+class PmTuneResult(ctypes.Structure):
+    _fields_ = [("row_variant", ctypes.c_int32), ("col_variant", ctypes.c_int32),
+                ("ms_per_iteration", (ctypes.c_double * 2) * 2)]
+
+
 class PmClusterStats(ctypes.Structure):
     _fields_ = [
         ("n_void", ctypes.c_int64), ("n_plastic", ctypes.c_int64), ("n_void_clusters", ctypes.c_int64),
@@ -126,6 +131,13 @@ SIGNATURES = [
       ctypes.POINTER(PmClusterStats), ctypes.c_void_p]),
     ("pm_five_point_average", ctypes.c_int,
      [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("pm_autotune_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    ("pm_autotune", ctypes.c_int,
+     [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+      ctypes.POINTER(PmTuneResult)]),
+    ("pm_set_tuning", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    ("pm_get_tuning", ctypes.c_int,
+     [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     ("pm_dg2_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(PmParams)]),
     ("pm_dg2_combine", ctypes.c_int,
      [ctypes.POINTER(PmParams), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),

@@ -2,6 +2,7 @@
 // of one load step.  All arithmetic of the method runs in the kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -79,7 +80,9 @@ Layout make_layout(const pm_params& q, bool tables, bool state) {
   Layout lo{};
   const size_t L = (size_t)q.L;
   const size_t fs = q.precision == PM_FP64 ? 8 : 4;
-  lo.nrow = q.precision == PM_FP64 ? pm::row_blocks<double>(q.L) : pm::row_blocks<float>(q.L);
+  // row-pass blocks of the larger of the two kernel variants
+  lo.nrow = q.precision == PM_FP64 ? std::max(pm::row_blocks<double>(q.L, 0), pm::row_blocks<double>(q.L, 1))
+                                   : std::max(pm::row_blocks<float>(q.L, 0), pm::row_blocks<float>(q.L, 1));
   lo.ndiv = std::max(pm::div_blocks(q.L), 4 * lo.nrow);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -163,11 +166,12 @@ int iterate_once(pm_solver* s, int slot_in_chunk) {
   const pm::Slot<T>* S = dslot<T>(s);
   hipEvent_t* ev = s->timing ? &s->tev[4 * slot_in_chunk] : nullptr;
   if (ev) PM_HIP(hipEventRecord(ev[0], s->stream));
-  PM_HIP(pm::launch_col<T>(L, pm::col_mode(pm::COL_ALL, green_kind(s->p)), S, 1, x, s->stream));
+  const pm::Tuning tv = pm::get_tuning(s->p.precision, L);
+  PM_HIP(pm::launch_col<T>(L, pm::col_mode(pm::COL_ALL, green_kind(s->p)), tv.col, S, 1, x, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[1], s->stream));
-  PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, S, 1, x, s->stream));
+  PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, tv.row, S, 1, x, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[2], s->stream));
-  PM_HIP(pm::launch_reduce<T>(S, 1, s->lo.nrow, s->stream));
+  PM_HIP(pm::launch_reduce<T>(S, 1, pm::row_blocks<T>(L, tv.row), s->stream));
   PM_HIP(pm::launch_div<T>(S, 1, L, 0, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[3], s->stream));
   return PM_OK;
@@ -200,15 +204,15 @@ int emit(pm_solver* s, pm_step_out* out) {
     x.eps_out = (T*)out->eps;
     x.plastic_out = out->plastic;
   }
-  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_EMIT, dslot<T>(s), 1, x, s->stream));
-  PM_HIP(pm::launch_reduce_emit<T>(dslot<T>(s), 1, s->lo.nrow, pm::GATE_ALL, s->stream));
+  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_EMIT, 0, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_reduce_emit<T>(dslot<T>(s), 1, pm::row_blocks<T>(s->p.L, 0), pm::GATE_ALL, s->stream));
   return PM_OK;
 }
 
 template <typename T>
 int init_state(pm_solver* s, const double* E) {
   const pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, E);
-  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_INIT, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_INIT, 0, dslot<T>(s), 1, x, s->stream));
   return PM_OK;
 }
 
@@ -315,8 +319,8 @@ template <typename T>
 int debug_forward(pm_solver* s, const void* d_real) {
   pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, nullptr);
   x.real_in = (const T*)d_real;
-  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_FWD, dslot<T>(s), 1, x, s->stream));
-  PM_HIP(pm::launch_col<T>(s->p.L, pm::COL_FWD, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_FWD, 0, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_col<T>(s->p.L, pm::COL_FWD, 0, dslot<T>(s), 1, x, s->stream));
   PM_HIP(hipStreamSynchronize(s->stream));
   return PM_OK;
 }
@@ -324,15 +328,16 @@ template <typename T>
 int debug_inverse(pm_solver* s, void* d_real) {
   pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, nullptr);
   x.real_out = (T*)d_real;
-  PM_HIP(pm::launch_col<T>(s->p.L, pm::COL_INV, dslot<T>(s), 1, x, s->stream));
-  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_INV, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_col<T>(s->p.L, pm::COL_INV, 0, dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_row<T>(s->p.L, pm::ROW_INV, 0, dslot<T>(s), 1, x, s->stream));
   PM_HIP(hipStreamSynchronize(s->stream));
   return PM_OK;
 }
 template <typename T>
 int debug_green(pm_solver* s, const double* E) {
   const pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_ALL, 1.0, E);
-  PM_HIP(pm::launch_col<T>(s->p.L, pm::col_mode(pm::COL_GREEN, green_kind(s->p)), dslot<T>(s), 1, x, s->stream));
+  PM_HIP(pm::launch_col<T>(s->p.L, pm::col_mode(pm::COL_GREEN, green_kind(s->p)), 0, dslot<T>(s), 1, x,
+                           s->stream));
   PM_HIP(hipStreamSynchronize(s->stream));
   return PM_OK;
 }
@@ -547,6 +552,101 @@ int pm_five_point_average(int32_t L, int32_t precision, int32_t nplanes, const v
   else
     PM_HIP(pm::launch_avg5<float>(L, nplanes, (const float*)d_in, (float*)d_out, (hipStream_t)stream));
   return PM_OK;
+}
+
+namespace {
+pm_params tune_params(int32_t L, int32_t precision) {
+  pm_params q{};
+  q.L = L;
+  q.mu = 1.0;
+  q.lambda = 2.0;
+  q.Y = 1.0;
+  q.max_iter = 1 << 30;   // never reached: the timing run must not halt
+  q.precision = precision;
+  return q;
+}
+}  // namespace
+
+size_t pm_autotune_workspace_bytes(int32_t L, int32_t precision) {
+  const pm_params q = tune_params(L, precision);
+  const size_t ws = pm_workspace_bytes(&q);
+  if (ws == 0) return 0;
+  return pmh::align_up(ws, 256) + (size_t)L * L;
+}
+
+int pm_set_tuning(int32_t L, int32_t precision, int32_t row_variant, int32_t col_variant) {
+  if (!pmh::is_pow2(L) || L < 4 || L > PM_MAX_L) return fail(PM_EINVAL, "L = %d out of range", L);
+  if (precision != PM_FP32 && precision != PM_FP64) return fail(PM_EINVAL, "precision must be PM_FP32 or PM_FP64");
+  if (pm::set_tuning(precision, L, {row_variant, col_variant}) != 0)
+    return fail(PM_EINVAL, "variants must be 0 or 1 (got %d, %d)", row_variant, col_variant);
+  return PM_OK;
+}
+
+int pm_get_tuning(int32_t L, int32_t precision, int32_t* row_variant, int32_t* col_variant) {
+  if (!pmh::is_pow2(L) || L < 4 || L > PM_MAX_L) return fail(PM_EINVAL, "L = %d out of range", L);
+  if (precision != PM_FP32 && precision != PM_FP64) return fail(PM_EINVAL, "precision must be PM_FP32 or PM_FP64");
+  const pm::Tuning t = pm::get_tuning(precision, L);
+  if (row_variant) *row_variant = t.row;
+  if (col_variant) *col_variant = t.col;
+  return PM_OK;
+}
+
+int pm_autotune(int32_t L, int32_t precision, int32_t iters, void* d_workspace, size_t workspace_bytes,
+                void* stream, pm_tune_result* out) {
+  if (!out || !d_workspace) return fail(PM_EINVAL, "NULL argument");
+  if (iters < 1 || iters > 100000) return fail(PM_EINVAL, "iters = %d must be in [1, 100000]", iters);
+  const size_t need = pm_autotune_workspace_bytes(L, precision);
+  if (need == 0) return fail(PM_EINVAL, "invalid L = %d or precision = %d", L, precision);
+  if (workspace_bytes < need) return fail(PM_EINVAL, "workspace of %zu bytes is smaller than the %zu required",
+                                          workspace_bytes, need);
+  const pm_params q = tune_params(L, precision);
+  const size_t ws = pmh::align_up(pm_workspace_bytes(&q), 256);
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* mask = (uint8_t*)d_workspace + ws;
+  PM_HIP(pm::launch_mask(mask, (long)L * L, 0.2, 0x5eedull, st));
+  pm_solver* s = nullptr;
+  int rc = pm_solver_create(&s, &q, mask, d_workspace, ws, stream);
+  if (rc != PM_OK) return rc;
+  const pm::Tuning before = pm::get_tuning(precision, L);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto finish = [&](int code) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    pm_solver_destroy(s);
+    if (code != PM_OK) pm::set_tuning(precision, L, before);
+    return code;
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return finish(fail(PM_EDEVICE, "hipEventCreate failed"));
+  const double E[3] = {0.01, 0.01, 0.005};
+  rc = precision == PM_FP64 ? init_state<double>(s, E) : init_state<float>(s, E);
+  if (rc != PM_OK) return finish(rc);
+  if (pm::launch_begin(s->st, E, q.mu, 0, 1, 0, st) != hipSuccess) return finish(fail(PM_EDEVICE, "launch failed"));
+  double best = 1e300;
+  pm::Tuning pick = {0, 0};
+  for (int r = 0; r < 2; ++r) {
+    for (int c = 0; c < 2; ++c) {
+      pm::set_tuning(precision, L, {r, c});
+      for (int i = 0; i < iters + 2; ++i) {
+        if (i == 2 && hipEventRecord(e0, st) != hipSuccess) return finish(fail(PM_EDEVICE, "hipEventRecord failed"));
+        rc = precision == PM_FP64 ? iterate_once<double>(s, 0) : iterate_once<float>(s, 0);
+        if (rc != PM_OK) return finish(rc);
+      }
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return finish(fail(PM_EDEVICE, "event failed"));
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return finish(fail(PM_EDEVICE, "hipEventElapsedTime failed"));
+      out->ms_per_iteration[r][c] = (double)ms / iters;
+      if (out->ms_per_iteration[r][c] < best) {
+        best = out->ms_per_iteration[r][c];
+        pick = {r, c};
+      }
+    }
+  }
+  pm::set_tuning(precision, L, pick);
+  out->row_variant = pick.row;
+  out->col_variant = pick.col;
+  return finish(PM_OK);
 }
 
 }  // extern "C"

@@ -163,8 +163,10 @@ struct pm_batch {
   bool use_graph;
   uint64_t table_version;    // bumped by every table upload
   uint64_t eager_version;    // table version of the last eager tick
-  uint64_t graph_version;    // table version and iteration count the graph holds
+  uint64_t graph_version;    // table version, iteration count and tuning the graph holds
   int graph_iters;
+  uint64_t graph_tuning;
+  uint64_t eager_tuning;
   hipGraphExec_t gexec;
 };
 
@@ -233,9 +235,10 @@ int iterate_group(pm_batch* b, int g) {
   const int L = group_L(g), n = b->grp_count[g];
   const pm::Slot<T>* tab = dev_table<T>(b, g);
   const pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_RUNNING, 1.0 / ((double)L * (double)L), nullptr);
-  PM_HIP(pm::launch_col<T>(L, pm::COL_ALL, tab, n, x, b->stream));
-  PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, tab, n, x, b->stream));
-  PM_HIP(pm::launch_reduce<T>(tab, n, pm::row_blocks<T>(L), b->stream));
+  const pm::Tuning tv = pm::get_tuning(group_fp64(g) ? PM_FP64 : PM_FP32, L);
+  PM_HIP(pm::launch_col<T>(L, pm::COL_ALL, tv.col, tab, n, x, b->stream));
+  PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, tv.row, tab, n, x, b->stream));
+  PM_HIP(pm::launch_reduce<T>(tab, n, pm::row_blocks<T>(L, tv.row), b->stream));
   PM_HIP(pm::launch_div<T>(tab, n, L, 0, b->stream));
   return PM_OK;
 }
@@ -246,8 +249,8 @@ int finish_group(pm_batch* b, int g) {
   const int L = group_L(g), n = b->grp_count[g];
   const pm::Slot<T>* tab = dev_table<T>(b, g);
   const pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_PENDING, 1.0, nullptr);
-  PM_HIP(pm::launch_row<T>(L, pm::ROW_EMIT, tab, n, x, b->stream));
-  PM_HIP(pm::launch_reduce_emit<T>(tab, n, pm::row_blocks<T>(L), pm::GATE_PENDING, b->stream));
+  PM_HIP(pm::launch_row<T>(L, pm::ROW_EMIT, 0, tab, n, x, b->stream));
+  PM_HIP(pm::launch_reduce_emit<T>(tab, n, pm::row_blocks<T>(L, 0), pm::GATE_PENDING, b->stream));
   PM_HIP(pm::launch_advance<T>(tab, n, b->stream));
   return PM_OK;
 }
@@ -306,6 +309,7 @@ int capture_tick(pm_batch* b, int iters) {
   }
   b->graph_version = b->table_version;
   b->graph_iters = iters;
+  b->graph_tuning = pm::tuning_generation();
   return PM_OK;
 }
 
@@ -325,7 +329,7 @@ int admit_impl(pm_batch* b, int i, const uint8_t* mask) {
   PM_HIP(pm::launch_begin(dev_state(b, i), h.E.data(), h.q.mu, 0, h.nsteps, h.hold, b->stream));
   // uniform start at E_1 (the state's E), as the first step of a solver
   const pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_ALL, 1.0, nullptr);
-  PM_HIP(pm::launch_row<T>(L, pm::ROW_INIT, own_desc<T>(b, i), 1, x, b->stream));
+  PM_HIP(pm::launch_row<T>(L, pm::ROW_INIT, 0, own_desc<T>(b, i), 1, x, b->stream));
   // the host copies above come from memory that stays alive with the slot;
   // wait so that a failure is reported here
   PM_HIP(hipStreamSynchronize(b->stream));
@@ -339,8 +343,8 @@ int fetch_impl(pm_batch* b, int i, pm_step_out* out) {
   x.sig_out = (T*)out->sigma;
   x.eps_out = (T*)out->eps;
   x.plastic_out = out->plastic;
-  PM_HIP(pm::launch_row<T>(h.q.L, pm::ROW_EMIT, own_desc<T>(b, i), 1, x, b->stream));
-  PM_HIP(pm::launch_reduce_emit<T>(own_desc<T>(b, i), 1, pm::row_blocks<T>(h.q.L), pm::GATE_ALL, b->stream));
+  PM_HIP(pm::launch_row<T>(h.q.L, pm::ROW_EMIT, 0, own_desc<T>(b, i), 1, x, b->stream));
+  PM_HIP(pm::launch_reduce_emit<T>(own_desc<T>(b, i), 1, pm::row_blocks<T>(h.q.L, 0), pm::GATE_ALL, b->stream));
   PM_HIP(hipMemcpyAsync(&b->hstates[i], dev_state(b, i), sizeof(DevState), hipMemcpyDeviceToHost, b->stream));
   PM_HIP(hipStreamSynchronize(b->stream));
   const DevState& st = b->hstates[i];
@@ -412,6 +416,8 @@ int pm_batch_create(pm_batch** out, void* d_pool, size_t pool_bytes, int32_t max
   b->eager_version = 0;
   b->graph_version = 0;
   b->graph_iters = 0;
+  b->graph_tuning = 0;
+  b->eager_tuning = 0;
   b->gexec = nullptr;
   auto cleanup = [&](int code) {
     if (b->stage) (void)hipHostFree(b->stage);
@@ -510,9 +516,10 @@ int pm_batch_tick(pm_batch* b, int32_t iters, int32_t* running) {
   if (rc != PM_OK) return rc;
   rc = rebuild_table(b);
   if (rc != PM_OK) return rc;
-  if (b->use_graph && b->eager_version == b->table_version) {
-    // the table ran eagerly once (kernel attributes set): replay a graph
-    if (!b->gexec || b->graph_version != b->table_version || b->graph_iters != iters) {
+  const uint64_t tgen = pm::tuning_generation();
+  if (b->use_graph && b->eager_version == b->table_version && b->eager_tuning == tgen) {
+    // the table ran eagerly once with this tuning (kernel attributes set): replay a graph
+    if (!b->gexec || b->graph_version != b->table_version || b->graph_iters != iters || b->graph_tuning != tgen) {
       rc = capture_tick(b, iters);
       if (rc != PM_OK) return rc;
     }
@@ -521,6 +528,7 @@ int pm_batch_tick(pm_batch* b, int32_t iters, int32_t* running) {
     rc = tick_launches(b, iters);
     if (rc != PM_OK) return rc;
     b->eager_version = b->table_version;
+    b->eager_tuning = tgen;
   }
   if (b->hi > 0)
     PM_HIP(hipMemcpyAsync(b->hstates, b->pool + b->fx.states, (size_t)b->hi * sizeof(DevState),

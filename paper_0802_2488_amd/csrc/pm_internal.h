@@ -100,12 +100,25 @@ __device__ __forceinline__ bool gated_out(const Extra<T>& x, const DevState* st_
   return (x.gate == GATE_RUNNING && st->halted) || (x.gate == GATE_PENDING && !st->pending);
 }
 
+// variant: 0 default, 1 the autotuner's alternative; it applies to ROW_ITER
+// and COL_ALL (any Green kind), other modes run variant 0.
 template <typename T>
-hipError_t launch_row(int L, int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st);
+hipError_t launch_row(int L, int mode, int variant, const Slot<T>* slots, int nslots, const Extra<T>& x,
+                      hipStream_t st);
 template <typename T>
-hipError_t launch_col(int L, int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st);
+hipError_t launch_col(int L, int mode, int variant, const Slot<T>* slots, int nslots, const Extra<T>& x,
+                      hipStream_t st);
 template <typename T>
-int row_blocks(int L);      // blocks per slot of the row pass
+int row_blocks(int L, int variant);   // blocks per slot of the row pass
+
+// Process-wide choice of the iteration-kernel variants per (precision, L);
+// the generation changes with every update.
+struct Tuning {
+  int row, col;
+};
+Tuning get_tuning(int precision, int L);
+int set_tuning(int precision, int L, Tuning t);
+uint64_t tuning_generation();
 template <typename T>
 int tile_width(int L);
 int div_blocks(int L);      // blocks per slot of the residual pass

@@ -808,47 +808,71 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
 }
 
 // ---------------------------------------------------------------------------
-// Launch configuration per (precision, L).  The column tile width W is also
-// the spectrum's tile width.
+// Launch configuration per (precision, L, variant).  Variant 0 is the
+// default; variant 1 the alternative the autotuner may choose for the
+// iteration kernels (another row radix, another column radix).  The
+// spectrum's tile width W is that of variant 0 for every variant, and the
+// columns per block of any variant divide it, so the data layout never
+// depends on the tuning.
 template <typename T, int L>
+struct ColTile {
+  static constexpr int CDEF = L < 8 ? 4 : (sizeof(T) == 8 ? (L >= 2048 ? PM_COL_R64 : 4) : (L >= 2048 ? PM_COL_R32 : 8));
+  static constexpr int CB = CDEF > L ? L : CDEF;
+  static constexpr int COL_RMAX = CB * 512 >= L ? CB : L / 512;
+  static constexpr int COL_TPF = L / COL_RMAX;
+  static constexpr int W_RAW = COL_TPF >= 256 ? (sizeof(T) == 8 ? 1 : PM_COL_W32) : (256 / COL_TPF > 16 ? 16 : 256 / COL_TPF);
+  static constexpr int W_CAP = W_RAW * COL_TPF > 1024 ? (1024 / COL_TPF > 0 ? 1024 / COL_TPF : 1) : W_RAW;
+  static constexpr int W = W_CAP > L / 2 ? L / 2 : W_CAP;
+};
+
+template <typename T, int L, int V>
 struct Cfg {
+  static constexpr bool F64 = sizeof(T) == 8;
   // Row pass.
-  static constexpr int RBASE = L < 8 ? 4 : (sizeof(T) == 8 ? PM_ROW_R64 : PM_ROW_R32);
+  static constexpr int RDEF = F64 ? PM_ROW_R64 : PM_ROW_R32;
+  static constexpr int RALT = F64 ? (PM_ROW_R64 == 4 ? 8 : 4) : (PM_ROW_R32 == 16 ? 8 : 16);
+  static constexpr int RBASE = L < 8 ? 4 : (V == 0 ? RDEF : RALT);
   static constexpr int RB = RBASE > L ? L : RBASE;
   static constexpr int RMAX = RB * PM_ROW_TPF_MAX >= L ? RB : L / PM_ROW_TPF_MAX;
   static constexpr int TPF = L / RMAX;
   static constexpr int ROW_TEAMS_RAW = TPF >= 256 ? 1 : 256 / TPF;
   static constexpr int ROW_TEAMS = ROW_TEAMS_RAW > L / 2 ? L / 2 : ROW_TEAMS_RAW;
-  // Column pass: larger radix for long columns, blocks of at most 512 threads.
-  static constexpr int CBASE = L < 8 ? 4 : (sizeof(T) == 8 ? (L >= 2048 ? PM_COL_R64 : 4) : (L >= 2048 ? PM_COL_R32 : 8));
+  // Column pass: larger radix for long columns, blocks of at most 512 threads
+  // (1024 for short columns).
+  static constexpr int CDEF = ColTile<T, L>::CDEF;
+  static constexpr int CALT = L < 8 ? 4 : (CDEF == 16 ? 8 : (CDEF == 8 ? (F64 ? 4 : 16) : 8));
+  static constexpr int CBASE = V == 0 ? CDEF : CALT;
   static constexpr int CB = CBASE > L ? L : CBASE;
   static constexpr int COL_RMAX = CB * 512 >= L ? CB : L / 512;
   static constexpr int COL_TPF = L / COL_RMAX;
-  static constexpr int COL_W_RAW = COL_TPF >= 256 ? (sizeof(T) == 8 ? 1 : PM_COL_W32) : (256 / COL_TPF > 16 ? 16 : 256 / COL_TPF);
-  static constexpr int COL_W_CAP = COL_W_RAW * COL_TPF > 1024 ? (1024 / COL_TPF > 0 ? 1024 / COL_TPF : 1) : COL_W_RAW;
-  static constexpr int COL_W = COL_W_CAP > L / 2 ? L / 2 : COL_W_CAP;
-  // columns per block: the tile width, except FP32 columns of 512 threads,
-  // which run one per block
-  static constexpr int COL_CB =
-      (sizeof(T) == 4 && COL_TPF >= 256) ? (COL_TPF >= 512 ? 1 : (PM_COL_CB32 < COL_W ? PM_COL_CB32 : COL_W)) : COL_W;
+  static constexpr int COL_W = ColTile<T, L>::W;
+  // columns per block: the tile width, except FP32 columns of 256 threads or
+  // more (PM_COL_CB32 per block; one per block at 512 threads); always a
+  // divisor of the tile width and at most 1024 threads per block
+  static constexpr int CB_RAW = COL_TPF >= 512 ? 1
+                                : (sizeof(T) == 4 && COL_TPF >= 256) ? PM_COL_CB32
+                                : (V == 0 ? COL_W : (256 / COL_TPF > 0 ? 256 / COL_TPF : 1));
+  static constexpr int CB_W = CB_RAW < COL_W ? CB_RAW : COL_W;
+  static constexpr int COL_CB = CB_W * COL_TPF > 1024 ? 1024 / COL_TPF : CB_W;
+  static_assert(COL_W % COL_CB == 0, "columns per block must divide the tile width");
 };
 
-template <typename T, int L>
+template <typename T, int L, int V>
 static size_t row_lds() {
-  using C = Cfg<T, L>;
+  using C = Cfg<T, L, V>;
   return RowLds<T, L, C::ROW_TEAMS, C::TPF>::bytes;
 }
-template <typename T, int L>
+template <typename T, int L, int V>
 static size_t col_lds() {
-  return (size_t)Cfg<T, L>::COL_CB * 2 * LdsSize<L>::value * sizeof(T);
+  return (size_t)Cfg<T, L, V>::COL_CB * 2 * LdsSize<L>::value * sizeof(T);
 }
 
-template <typename T, int L, int MODE>
+template <typename T, int L, int V, int MODE>
 static hipError_t launch_row_LM(const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
-  using C = Cfg<T, L>;
+  using C = Cfg<T, L, V>;
   auto kern = k_row<T, L, C::RMAX, C::ROW_TEAMS, C::COL_W, MODE>;
   static bool attr = false;
-  const size_t lds = row_lds<T, L>();
+  const size_t lds = row_lds<T, L, V>();
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -859,12 +883,12 @@ static hipError_t launch_row_LM(const Slot<T>* slots, int nslots, const Extra<T>
   return hipGetLastError();
 }
 
-template <typename T, int L, int MODE>
+template <typename T, int L, int V, int MODE>
 static hipError_t launch_col_LM(const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
-  using C = Cfg<T, L>;
+  using C = Cfg<T, L, V>;
   auto kern = k_column<T, L, C::COL_RMAX, C::COL_W, C::COL_CB, MODE>;
   static bool attr = false;
-  const size_t lds = col_lds<T, L>();
+  const size_t lds = col_lds<T, L, V>();
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -875,37 +899,49 @@ static hipError_t launch_col_LM(const Slot<T>* slots, int nslots, const Extra<T>
   return hipGetLastError();
 }
 
+// The tuned variant applies to the iteration kernels (ROW_ITER, COL_ALL of
+// every Green kind); the other modes always run variant 0.
 template <typename T, int L>
-static hipError_t launch_row_L(int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
+static hipError_t launch_row_L(int mode, int v, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
   switch (mode) {
-    case ROW_ITER: return launch_row_LM<T, L, ROW_ITER>(slots, nslots, x, st);
-    case ROW_INIT: return launch_row_LM<T, L, ROW_INIT>(slots, nslots, x, st);
-    case ROW_FWD: return launch_row_LM<T, L, ROW_FWD>(slots, nslots, x, st);
-    case ROW_INV: return launch_row_LM<T, L, ROW_INV>(slots, nslots, x, st);
-    case ROW_EMIT: return launch_row_LM<T, L, ROW_EMIT>(slots, nslots, x, st);
+    case ROW_ITER:
+      return v ? launch_row_LM<T, L, 1, ROW_ITER>(slots, nslots, x, st)
+               : launch_row_LM<T, L, 0, ROW_ITER>(slots, nslots, x, st);
+    case ROW_INIT: return launch_row_LM<T, L, 0, ROW_INIT>(slots, nslots, x, st);
+    case ROW_FWD: return launch_row_LM<T, L, 0, ROW_FWD>(slots, nslots, x, st);
+    case ROW_INV: return launch_row_LM<T, L, 0, ROW_INV>(slots, nslots, x, st);
+    case ROW_EMIT: return launch_row_LM<T, L, 0, ROW_EMIT>(slots, nslots, x, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int L>
-static hipError_t launch_col_L(int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
+static hipError_t launch_col_L(int mode, int v, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
   switch (mode) {
-    case COL_ALL: return launch_col_LM<T, L, COL_ALL>(slots, nslots, x, st);
-    case COL_FWD: return launch_col_LM<T, L, COL_FWD>(slots, nslots, x, st);
-    case COL_INV: return launch_col_LM<T, L, COL_INV>(slots, nslots, x, st);
-    case COL_GREEN: return launch_col_LM<T, L, COL_GREEN>(slots, nslots, x, st);
-    case col_mode(COL_ALL, GK_DG1): return launch_col_LM<T, L, col_mode(COL_ALL, GK_DG1)>(slots, nslots, x, st);
-    case col_mode(COL_ALL, GK_CG1): return launch_col_LM<T, L, col_mode(COL_ALL, GK_CG1)>(slots, nslots, x, st);
-    case col_mode(COL_GREEN, GK_DG1): return launch_col_LM<T, L, col_mode(COL_GREEN, GK_DG1)>(slots, nslots, x, st);
-    case col_mode(COL_GREEN, GK_CG1): return launch_col_LM<T, L, col_mode(COL_GREEN, GK_CG1)>(slots, nslots, x, st);
+    case COL_ALL:
+      return v ? launch_col_LM<T, L, 1, COL_ALL>(slots, nslots, x, st)
+               : launch_col_LM<T, L, 0, COL_ALL>(slots, nslots, x, st);
+    case col_mode(COL_ALL, GK_DG1):
+      return v ? launch_col_LM<T, L, 1, col_mode(COL_ALL, GK_DG1)>(slots, nslots, x, st)
+               : launch_col_LM<T, L, 0, col_mode(COL_ALL, GK_DG1)>(slots, nslots, x, st);
+    case col_mode(COL_ALL, GK_CG1):
+      return v ? launch_col_LM<T, L, 1, col_mode(COL_ALL, GK_CG1)>(slots, nslots, x, st)
+               : launch_col_LM<T, L, 0, col_mode(COL_ALL, GK_CG1)>(slots, nslots, x, st);
+    case COL_FWD: return launch_col_LM<T, L, 0, COL_FWD>(slots, nslots, x, st);
+    case COL_INV: return launch_col_LM<T, L, 0, COL_INV>(slots, nslots, x, st);
+    case COL_GREEN: return launch_col_LM<T, L, 0, COL_GREEN>(slots, nslots, x, st);
+    case col_mode(COL_GREEN, GK_DG1): return launch_col_LM<T, L, 0, col_mode(COL_GREEN, GK_DG1)>(slots, nslots, x, st);
+    case col_mode(COL_GREEN, GK_CG1): return launch_col_LM<T, L, 0, col_mode(COL_GREEN, GK_CG1)>(slots, nslots, x, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int L>
-static int row_grid_L() { return (L / 2) / Cfg<T, L>::ROW_TEAMS; }
+static int row_grid_L(int v) {
+  return v ? (L / 2) / Cfg<T, L, 1>::ROW_TEAMS : (L / 2) / Cfg<T, L, 0>::ROW_TEAMS;
+}
 template <typename T, int L>
-static int tile_w_L() { return Cfg<T, L>::COL_W; }
+static int tile_w_L(int) { return ColTile<T, L>::W; }
 
 #define PM_DISPATCH_L(FN, T, L, ...)            \
   switch (L) {                                  \
@@ -925,38 +961,40 @@ static int tile_w_L() { return Cfg<T, L>::COL_W; }
   }
 
 template <typename T>
-hipError_t launch_row(int L, int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
-  PM_DISPATCH_L(launch_row_L, T, L, mode, slots, nslots, x, st)
+hipError_t launch_row(int L, int mode, int variant, const Slot<T>* slots, int nslots, const Extra<T>& x,
+                      hipStream_t st) {
+  PM_DISPATCH_L(launch_row_L, T, L, mode, variant, slots, nslots, x, st)
 }
 template <typename T>
-hipError_t launch_col(int L, int mode, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
-  PM_DISPATCH_L(launch_col_L, T, L, mode, slots, nslots, x, st)
+hipError_t launch_col(int L, int mode, int variant, const Slot<T>* slots, int nslots, const Extra<T>& x,
+                      hipStream_t st) {
+  PM_DISPATCH_L(launch_col_L, T, L, mode, variant, slots, nslots, x, st)
 }
 
-#define PM_DISPATCH_INT(FN, T, L)     \
-  switch (L) {                        \
-    case 4: return FN<T, 4>();        \
-    case 8: return FN<T, 8>();        \
-    case 16: return FN<T, 16>();      \
-    case 32: return FN<T, 32>();      \
-    case 64: return FN<T, 64>();      \
-    case 128: return FN<T, 128>();    \
-    case 256: return FN<T, 256>();    \
-    case 512: return FN<T, 512>();    \
-    case 1024: return FN<T, 1024>();  \
-    case 2048: return FN<T, 2048>();  \
-    case 4096: return FN<T, 4096>();  \
-    case 8192: return FN<T, 8192>();  \
-    default: return -1;               \
+#define PM_DISPATCH_INT(FN, T, L, V)    \
+  switch (L) {                          \
+    case 4: return FN<T, 4>(V);         \
+    case 8: return FN<T, 8>(V);         \
+    case 16: return FN<T, 16>(V);       \
+    case 32: return FN<T, 32>(V);       \
+    case 64: return FN<T, 64>(V);       \
+    case 128: return FN<T, 128>(V);     \
+    case 256: return FN<T, 256>(V);     \
+    case 512: return FN<T, 512>(V);     \
+    case 1024: return FN<T, 1024>(V);   \
+    case 2048: return FN<T, 2048>(V);   \
+    case 4096: return FN<T, 4096>(V);   \
+    case 8192: return FN<T, 8192>(V);   \
+    default: return -1;                 \
   }
 
 template <typename T>
-int row_blocks(int L) {
-  PM_DISPATCH_INT(row_grid_L, T, L)
+int row_blocks(int L, int variant) {
+  PM_DISPATCH_INT(row_grid_L, T, L, variant)
 }
 template <typename T>
 int tile_width(int L) {
-  PM_DISPATCH_INT(tile_w_L, T, L)
+  PM_DISPATCH_INT(tile_w_L, T, L, 0)
 }
 
 }  // namespace pm

@@ -1,5 +1,7 @@
 // Reductions, convergence logic, equilibrium residual, output sums and the
 // mask generator.  One block per slot for the final reductions.
+#include <atomic>
+
 #include "pm_kernels.hpp"
 
 namespace pm {
@@ -244,6 +246,34 @@ __global__ void __launch_bounds__(256) k_mask(uint8_t* __restrict__ out, long np
 }
 
 // ---------------------------------------------------------------------------
+// Tuning table: entry [precision][log2 L] holds row | col << 1.
+namespace {
+std::atomic<int> g_tune[2][14];
+std::atomic<uint64_t> g_tune_gen{1};
+int log2_of(int L) {
+  int k = 0;
+  while ((1 << k) < L) ++k;
+  return k;
+}
+}  // namespace
+
+Tuning get_tuning(int precision, int L) {
+  const int k = log2_of(L);
+  if (k < 2 || k > 13 || (precision != 0 && precision != 1)) return {0, 0};
+  const int v = g_tune[precision][k].load(std::memory_order_relaxed);
+  return {v & 1, (v >> 1) & 1};
+}
+
+int set_tuning(int precision, int L, Tuning t) {
+  const int k = log2_of(L);
+  if (k < 2 || k > 13 || (precision != 0 && precision != 1) || (t.row & ~1) || (t.col & ~1)) return -1;
+  g_tune[precision][k].store(t.row | (t.col << 1), std::memory_order_relaxed);
+  g_tune_gen.fetch_add(1, std::memory_order_relaxed);
+  return 0;
+}
+
+uint64_t tuning_generation() { return g_tune_gen.load(std::memory_order_relaxed); }
+
 int div_blocks(int L) {
   const long npx = (long)L * L;
   long g = (npx + 255) / 256;

@@ -115,7 +115,7 @@ class Solver:
 
     # -- kernel-level hooks -------------------------------------------------
     def buffers(self):
-        """Views of the workspace: eps state (4, L, L) and the raw half
+        """Views of the workspace: the stress state (4, L, L) and the raw half
         spectrum (L*L/2*3*2,) in the tiled layout of pm_spectrum_tile."""
         e = ctypes.c_void_p()
         s = ctypes.c_void_p()
@@ -150,3 +150,31 @@ def solve_path(mask, params: PmParams, E_path, fields=True):
         return [s.step(E, fields=fields) for E in E_path]
     finally:
         s.close()
+
+
+def autotune(L: int, precision="fp32", iters=20, device="cuda") -> dict:
+    """Time the kernel variants for (L, precision) and put the fastest into effect."""
+    prec = {"fp32": PM_FP32, "fp64": PM_FP64}[precision]
+    n = lib().pm_autotune_workspace_bytes(L, prec)
+    if n == 0:
+        raise _lib.PmError(_lib.PM_EINVAL, "pm_autotune_workspace_bytes")
+    ws = torch.empty(n + 256, dtype=torch.uint8, device=device)
+    base = ws.data_ptr()
+    out = _lib.PmTuneResult()
+    check(lib().pm_autotune(L, prec, iters, base + (-base) % 256, n, _stream(device), ctypes.byref(out)),
+          "pm_autotune")
+    return {"row_variant": out.row_variant, "col_variant": out.col_variant,
+            "ms_per_iteration": [[out.ms_per_iteration[r][c] for c in range(2)] for r in range(2)]}
+
+
+def set_tuning(L: int, precision="fp32", row_variant=0, col_variant=0):
+    prec = {"fp32": PM_FP32, "fp64": PM_FP64}[precision]
+    check(lib().pm_set_tuning(L, prec, row_variant, col_variant), "pm_set_tuning")
+
+
+def get_tuning(L: int, precision="fp32"):
+    prec = {"fp32": PM_FP32, "fp64": PM_FP64}[precision]
+    r, c = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().pm_get_tuning(L, prec, ctypes.byref(r), ctypes.byref(c)), "pm_get_tuning")
+    return r.value, c.value
+
