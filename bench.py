@@ -204,7 +204,19 @@ def run_sequential(jobs):
     return dict(value=work / dt, seconds=dt, pixel_iters=work)
 
 
+def autotune_sizes(sizes, precision="fp32"):
+    """Autotune the kernel variants of each size (not timed); returns the choices."""
+    from paper_0802_2488_amd import solver as pms
+
+    out = {}
+    for L in sizes:
+        r = pms.autotune(L, precision, iters=10 if L >= 2048 else 30)
+        out[str(L)] = r
+    return out
+
+
 def batched_section(a):
+    tuning = autotune_sizes((128, 256, 512))
     jobs = batch_jobs(a.batch_n, a.batch_max_iter)
     full = run_batch(jobs, a.tick)
     print(f"# batched done: {full['value']:.4e} px-iter/s in {full['seconds']:.1f} s", file=sys.stderr, flush=True)
@@ -220,6 +232,7 @@ def batched_section(a):
         "value": full["value"], "unit": "pixel-iters/s", "seconds": full["seconds"],
         "pixel_iters": full["pixel_iters"], "steps": full["steps"], "converged_steps": full["converged_steps"],
         "pool_bytes": full["pool_bytes"],
+        "autotuned": tuning,
         "same_work_sample": {"what": "realizations 0-15, load steps 1-3",
                              "batched": sb["value"], "sequential": sq["value"],
                              "speedup": sb["value"] / sq["value"]},
@@ -329,19 +342,28 @@ def next_rows_section(plastic_4096=None):
                            "stats": st, "indicators": clusters.indicators(st, L)}
         print(f"# clusters done: {1e3 * tm:.2f} ms", file=sys.stderr, flush=True)
     # iterations to a tolerance with the tensor of eq. 3, DG1 and CG1 (Sec. 2 compares the methods)
+    # The equilibrium indicator uses the backward differences of eq. 1, whose
+    # equilibrium DG1 and CG1 do not solve; methods are compared by the
+    # iterations until the change and constraint indicators pass.
     L = 128
     m = pms.device_mask(L, 0.1, 0)
+    E1 = synth.load_path("equibiaxial", 10, 3.0)[0]
     its = {}
-    for name, v in (("eq3", 0), ("DG1", 4), ("CG1", 5)):
-        q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.5, lam0=1.0, tol=1e-5, max_iter=4000,
+    for name, v in (("DG eq.3", 0), ("DG1", 4), ("CG1", 5)):
+        q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.5, lam0=1.0, tol=1e-6, eta_eq=1e30, max_iter=4000,
                             precision="fp64", green_variant=v)
         s = pms.Solver(m, q)
-        r = s.step(synth.load_path("equibiaxial", 10, 3.0)[0], fields=False)
-        its[name] = {"iters": r.iters, "converged": r.converged, "res_eq": r.res_eq, "res_mac": r.res_mac,
-                     "res_cmp": r.res_cmp}
+        r = s.step(E1, fields=False)
+        its[name] = {"iters": r.iters, "converged": r.converged, "res_eq_backward_difference": r.res_eq}
         s.close()
+    q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.5, lam0=1.0, tol=1e-6, eta_eq=1e30, max_iter=4000,
+                        precision="fp64")
+    st = dg2.solve_path(m, q, [E1], fields=False)[0]
+    its["DG2"] = {"iters_per_variant": [r.iters for r in st.records],
+                  "converged": all(r.status == 1 for r in st.records)}
     out["method_iterations"] = {"workload": f"L={L}, f=0.1, equibiaxial load step 1 of 10, reference medium "
-                                            "0.5x matrix, tol 1e-5, FP64, max_iter 4000", **its}
+                                            "0.5x matrix, change and constraint indicators < 1e-6, FP64, "
+                                            "max_iter 4000", **its}
     return out
 
 
@@ -381,6 +403,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     L = a.L
+    tuned = {"fp32": autotune_sizes((L,), "fp32")[str(L)]}
+    if not a.no_fp64:
+        tuned["fp64"] = autotune_sizes((L,), "fp64")[str(L)]
     r32 = run_gpu(L, "fp32", a.steps, a.warmup, a.max_iter)
     print(f"# fp32 done: {r32['value']:.4e} px-iter/s over {r32['iters']} iterations", file=sys.stderr, flush=True)
     row_b, col_b = algorithmic_bytes(L, 4)
@@ -418,7 +443,7 @@ def main():
                                f"tol 1e-6, FP32 fields + FP64 norms; step = one load step (max_iter "
                                f"{a.max_iter})",
                    "L": L, "f": 0.3, "seed": 0, "load_steps_timed": list(range(a.warmup + 1, a.warmup + a.steps + 1)),
-                   "parallelism": "1 GPU"},
+                   "parallelism": "1 GPU", "autotuned_variants": tuned},
         "roofline": {"bound": "hbm", "kernel": "k_row (inverse row FFT + pointwise step + forward row FFT)",
                      "achieved": row_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": row_gbs / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic["k_row"],
