@@ -55,6 +55,9 @@
 #ifndef PM_COL_CB32
 #define PM_COL_CB32 2         // columns per block, FP32, columns of 256 threads
 #endif
+#ifndef PM_COL_LDS_SKEW
+#define PM_COL_LDS_SKEW 16    // words between the FFT buffers of a block's columns, beyond their size
+#endif
 #ifndef PM_COL_WPE
 #define PM_COL_WPE 2
 #endif
@@ -727,9 +730,13 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
   const Slot<T>& S = slots[blockIdx.x / BPS];
   if (gated_out(x, S.st)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // The column index runs fastest across lanes, so a wave's loads cover
+  // whole tile rows.  Neighbouring lanes then address two columns' FFT
+  // buffers at the same index; the buffers are skewed by PM_COL_LDS_SKEW
+  // words so those accesses fall in different banks.
   const int wb = threadIdx.x % CB;        // column within the block
   const int t = threadIdx.x / CB;
-  T* lre = reinterpret_cast<T*>(smem_raw) + wb * 2 * LS;
+  T* lre = reinterpret_cast<T*>(smem_raw) + wb * (2 * LS + PM_COL_LDS_SKEW);
   T* lim = lre + LS;
   const int g = xcd_remap(blockIdx.x % BPS, BPS);
   const int m1 = g * CB + wb;
@@ -864,7 +871,7 @@ static size_t row_lds() {
 }
 template <typename T, int L, int V>
 static size_t col_lds() {
-  return (size_t)Cfg<T, L, V>::COL_CB * 2 * LdsSize<L>::value * sizeof(T);
+  return (size_t)Cfg<T, L, V>::COL_CB * (2 * LdsSize<L>::value + PM_COL_LDS_SKEW) * sizeof(T);
 }
 
 template <typename T, int L, int V, int MODE>
