@@ -317,39 +317,87 @@ constexpr int divisor_upto(int n, int cap) {
   return d;
 }
 
-// Copy row r (0 or 1) of a row pair's slice of the half spectrum between HBM
-// and its LDS stage in 16-byte units: in tile j the row holds WT 3
-// contiguous complex values, and the stage keeps them in tile order.
-template <typename T, int L, int WT, int TPF, bool TO_LDS>
-__device__ __forceinline__ void stage_row(gptr<cx<T>> __restrict__ g, cx<T>* __restrict__ st, int t, int r) {
-  constexpr int CPT = WT * 3;                           // complex values per tile and row
-  constexpr int UPT = CPT * (int)sizeof(cx<T>) / 16;    // 16-byte units per tile and row
-  constexpr int NU = (L / 2 / WT) * UPT;
-  static_assert((CPT * sizeof(cx<T>)) % 16 == 0, "a tile row must be a whole number of 16-byte units");
+// A row pair's slice of the half spectrum in 16-byte units: in tile j each
+// row holds WT 3 contiguous complex values (UPT units) and row b follows row
+// a.  Unit u of row a sits at unit gidx(u) from the pair's base and the same
+// unit of row b UPT units further; the LDS stage keeps one row in tile order.
+template <typename T, int L, int WT, int TPF>
+struct RowUnits {
   using u4 = unsigned __attribute__((ext_vector_type(4)));
+  static constexpr int CPT = WT * 3;                           // complex values per tile and row
+  static constexpr int UPT = CPT * (int)sizeof(cx<T>) / 16;    // 16-byte units per tile and row
+  static constexpr int NU = (L / 2 / WT) * UPT;
+  static constexpr int PER = NU / TPF;                         // units per thread and row
+  static_assert((CPT * sizeof(cx<T>)) % 16 == 0, "a tile row must be a whole number of 16-byte units");
   static_assert(NU % TPF == 0, "the copy must split evenly over the team");
-  constexpr int PER = NU / TPF;
-  gptr<const u4> __restrict__ gs = (gptr<const u4>)g;
-  gptr<u4> __restrict__ gd = (gptr<u4>)g;
-  u4* __restrict__ ls = reinterpret_cast<u4*>(st);
-  auto gidx = [&](int u) {
+  static __device__ __forceinline__ unsigned gidx(int u) {
     const int j = u / UPT, k = u - j * UPT;
-    return (unsigned)j * (L * WT * 3 * (int)sizeof(cx<T>) / 16) + r * UPT + k;
-  };
-  if constexpr (TO_LDS) {
-    // loads are issued in groups of G before the group's LDS writes
-    constexpr int G = divisor_upto(PER, PM_STAGE_INFLIGHT);
+    return (unsigned)j * (L * WT * 3 * (int)sizeof(cx<T>) / 16) + k;
+  }
+};
+
+// Both rows of a pair from HBM: row a into the LDS stage, row b into
+// registers.  The two rows of a tile are adjacent, so loading them together
+// brings each cache line in once.
+template <typename T, int L, int WT, int TPF>
+__device__ __forceinline__ void stage_pair_in(gptr<cx<T>> __restrict__ g, cx<T>* __restrict__ st, int t,
+                                              typename RowUnits<T, L, WT, TPF>::u4 (&hold)[RowUnits<T, L, WT, TPF>::PER]) {
+  using R = RowUnits<T, L, WT, TPF>;
+  using u4 = typename R::u4;
+  gptr<const u4> __restrict__ gs = (gptr<const u4>)g;
+  u4* __restrict__ ls = reinterpret_cast<u4*>(st);
+  constexpr int G = divisor_upto(R::PER, PM_STAGE_INFLIGHT);
 #pragma unroll
-    for (int i0 = 0; i0 < PER; i0 += G) {
-      u4 buf[G];
+  for (int i0 = 0; i0 < R::PER; i0 += G) {
+    u4 buf[G];
 #pragma unroll
-      for (int i = 0; i < G; ++i) buf[i] = gs[gidx(t + (i0 + i) * TPF)];
-#pragma unroll
-      for (int i = 0; i < G; ++i) ls[t + (i0 + i) * TPF] = buf[i];
+    for (int i = 0; i < G; ++i) {
+      const unsigned gi = R::gidx(t + (i0 + i) * TPF);
+      buf[i] = gs[gi];
+      hold[i0 + i] = gs[gi + R::UPT];
     }
-  } else {
-#pragma unroll 1
-    for (int i = 0; i < PER; ++i) gd[gidx(t + i * TPF)] = ls[t + i * TPF];
+#pragma unroll
+    for (int i = 0; i < G; ++i) ls[t + (i0 + i) * TPF] = buf[i];
+  }
+}
+
+// Row b, held in registers, into the LDS stage.
+template <typename T, int L, int WT, int TPF>
+__device__ __forceinline__ void hold_to_stage(cx<T>* __restrict__ st, int t,
+                                              const typename RowUnits<T, L, WT, TPF>::u4 (&hold)[RowUnits<T, L, WT, TPF>::PER]) {
+  using R = RowUnits<T, L, WT, TPF>;
+  using u4 = typename R::u4;
+  u4* __restrict__ ls = reinterpret_cast<u4*>(st);
+#pragma unroll
+  for (int i = 0; i < R::PER; ++i) ls[t + i * TPF] = hold[i];
+}
+
+// Row a, staged in LDS, into registers.
+template <typename T, int L, int WT, int TPF>
+__device__ __forceinline__ void stage_to_hold(const cx<T>* __restrict__ st, int t,
+                                              typename RowUnits<T, L, WT, TPF>::u4 (&hold)[RowUnits<T, L, WT, TPF>::PER]) {
+  using R = RowUnits<T, L, WT, TPF>;
+  using u4 = typename R::u4;
+  const u4* __restrict__ ls = reinterpret_cast<const u4*>(st);
+#pragma unroll
+  for (int i = 0; i < R::PER; ++i) hold[i] = ls[t + i * TPF];
+}
+
+// Both rows of a pair to HBM: row a from registers, row b from the LDS stage,
+// so each cache line is written whole at once.
+template <typename T, int L, int WT, int TPF>
+__device__ __forceinline__ void stage_pair_out(gptr<cx<T>> __restrict__ g, const cx<T>* __restrict__ st, int t,
+                                               const typename RowUnits<T, L, WT, TPF>::u4 (&hold)[RowUnits<T, L, WT, TPF>::PER]) {
+  using R = RowUnits<T, L, WT, TPF>;
+  using u4 = typename R::u4;
+  gptr<u4> __restrict__ gd = (gptr<u4>)g;
+  const u4* __restrict__ ls = reinterpret_cast<const u4*>(st);
+#pragma unroll
+  for (int i = 0; i < R::PER; ++i) {
+    const int u = t + i * TPF;
+    const unsigned gi = R::gidx(u);
+    gd[gi] = hold[i];
+    gd[gi + R::UPT] = ls[u];
   }
 }
 
@@ -434,8 +482,9 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       }
     };
     if constexpr (STAGED) {
-      // row a: Za = 11a + i 22a and the 12a part of Zc
-      stage_row<T, L, WT, TPF, true>(gbase, stg, t, 0);
+      // row a: Za = 11a + i 22a and the 12a part of Zc; row b waits in registers
+      typename RowUnits<T, L, WT, TPF>::u4 hold[RowUnits<T, L, WT, TPF>::PER];
+      stage_pair_in<T, L, WT, TPF>(gbase, stg, t, hold);
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < RMAX; ++s) {
@@ -446,7 +495,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       }
       __syncthreads();
       // row b: Zb = 11b + i 22b, and Zc = 12a + i 12b
-      stage_row<T, L, WT, TPF, true>(gbase, stg, t, 1);
+      hold_to_stage<T, L, WT, TPF>(stg, t, hold);
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < RMAX; ++s) {
@@ -605,11 +654,12 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
     __syncthreads();
     put_row<T, L, H, WT, SSTRIDE>(stg, t, 0, xa, ya, xc);
     __syncthreads();
-    stage_row<T, L, WT, TPF, false>(gbase, stg, t, 0);
+    typename RowUnits<T, L, WT, TPF>::u4 hold[RowUnits<T, L, WT, TPF>::PER];
+    stage_to_hold<T, L, WT, TPF>(stg, t, hold);
     __syncthreads();
     put_row<T, L, H, WT, SSTRIDE>(stg, t, 0, xb, yb, yc);
     __syncthreads();
-    stage_row<T, L, WT, TPF, false>(gbase, stg, t, 1);
+    stage_pair_out<T, L, WT, TPF>(gbase, stg, t, hold);
   } else {
     put_row<T, L, H, WT, GSTRIDE>(gbase, t, 0, xa, ya, xc);
     put_row<T, L, H, WT, GSTRIDE>(gbase, t, 1, xb, yb, yc);
