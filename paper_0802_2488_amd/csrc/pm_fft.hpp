@@ -275,12 +275,20 @@ __device__ __forceinline__ void apply_seeds(cx<T>* u, const cx<T> (&sd)[4]) {
   }
 }
 
-// One Stockham stage.  Input: stage 0 takes pattern A from v; later stages
-// read LDS.  Output: the last stage writes pattern A to v; earlier stages
-// write LDS.  Barriers are placed so one LDS buffer can be reused.
-template <int DIR, typename T, int N, int RMAX, int STAGE>
-__device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__ lre, T* __restrict__ lim,
-                                               int t, const StageSeeds<DIR, T, N, RMAX, STAGE>& sd) {
+// LDS exchange buffers of one transform team, from a base pointer: buffer
+// b holds real parts at base + 2 b S and imaginary parts at base + (2 b + 1) S,
+// S = LdsSize<N>::value.  With one buffer a stage's writes wait at a barrier
+// until every thread has read the previous stage; with two (DB),
+// consecutive exchanges alternate between the buffers, so only the barrier
+// between an exchange's writes and its reads remains.
+//
+// One Stockham stage, the X-th exchange of a chain of transforms.  Input:
+// stage 0 takes pattern A from v; later stages read exchange X - 1 from LDS.
+// Output: the last stage writes pattern A to v; earlier stages write
+// exchange X to LDS.
+template <int DIR, typename T, int N, int RMAX, int STAGE, bool DB, int X>
+__device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__ xb, int t,
+                                               const StageSeeds<DIR, T, N, RMAX, STAGE>& sd) {
   using P = Plan<N, RMAX>;
   constexpr int R = P::radix(STAGE);
   constexpr int NS = P::ns(STAGE);
@@ -288,6 +296,8 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__
   constexpr int B = RMAX / R;
   constexpr bool FIRST = STAGE == 0;
   constexpr bool LAST = STAGE == P::NSTAGE - 1;
+  constexpr int S = LdsSize<N>::value;
+  constexpr int RD = DB ? ((X - 1) & 1) : 0, WR = DB ? (X & 1) : 0;
   cx<T> u[RMAX];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
@@ -298,7 +308,7 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__
       } else {
         const int j = t + b * TPF;
         const int idx = lpad(j + r * (N / R));
-        u[b * R + r] = {lre[idx], lim[idx]};
+        u[b * R + r] = {xb[2 * RD * S + idx], xb[(2 * RD + 1) * S + idx]};
       }
     }
   }
@@ -313,7 +323,9 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b + B * r] = u[b * R + r];
   } else {
-    __syncthreads();
+    if constexpr (!DB) __syncthreads();
+    T* __restrict__ wre = xb + 2 * WR * S;
+    T* __restrict__ wim = xb + (2 * WR + 1) * S;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = t + b * TPF;
@@ -321,38 +333,60 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = lpad(base + r * NS);
-        lre[idx] = u[b * R + r].re;
-        lim[idx] = u[b * R + r].im;
+        wre[idx] = u[b * R + r].re;
+        wim[idx] = u[b * R + r].im;
       }
     }
     __syncthreads();
   }
 }
 
-template <int DIR, typename T, int N, int RMAX, int STAGE>
-__device__ __forceinline__ void fft_stages(cx<T> (&v)[RMAX], T* lre, T* lim, int t, gptr<const cx<T>> tw,
+template <int DIR, typename T, int N, int RMAX, int STAGE, bool DB, int X0>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[RMAX], T* xb, int t, gptr<const cx<T>> tw,
                                            const StageSeeds<DIR, T, N, RMAX, STAGE>& cur) {
   if constexpr (STAGE + 1 < Plan<N, RMAX>::NSTAGE) {
     StageSeeds<DIR, T, N, RMAX, STAGE + 1> nxt;
     load_seeds<DIR, T, N, RMAX, STAGE + 1>(nxt, tw, t);
-    stockham_stage<DIR, T, N, RMAX, STAGE>(v, lre, lim, t, cur);
-    fft_stages<DIR, T, N, RMAX, STAGE + 1>(v, lre, lim, t, tw, nxt);
+    stockham_stage<DIR, T, N, RMAX, STAGE, DB, X0 + STAGE>(v, xb, t, cur);
+    fft_stages<DIR, T, N, RMAX, STAGE + 1, DB, X0>(v, xb, t, tw, nxt);
   } else {
-    stockham_stage<DIR, T, N, RMAX, STAGE>(v, lre, lim, t, cur);
+    stockham_stage<DIR, T, N, RMAX, STAGE, DB, X0 + STAGE>(v, xb, t, cur);
   }
+}
+
+// Exchanges (LDS round trips) of one length-N transform.
+template <int N, int RMAX>
+constexpr int fft_exchanges() {
+  return Plan<N, RMAX>::NSTAGE - 1;
 }
 
 // Length-N transform of one signal held in pattern A by a team of Plan::TPF
 // threads; every thread of the block must call it (it contains barriers).
-template <int DIR, typename T, int N, int RMAX>
-__device__ __forceinline__ void fft(cx<T> (&v)[RMAX], T* lre, T* lim, int t, gptr<const cx<T>> tw) {
+// X0 numbers its first exchange within a chain of transforms.  With two
+// buffers the first write is not preceded by a barrier: the caller either
+// starts a chain behind one, or continues a chain (X0 = exchanges so far),
+// in which case the buffer it writes was last read before the barrier of
+// the previous exchange.
+template <int DIR, typename T, int N, int RMAX, bool DB = false, int X0 = 0>
+__device__ __forceinline__ void fft(cx<T> (&v)[RMAX], T* xb, int t, gptr<const cx<T>> tw) {
   // An opaque copy of the table pointer behind a compiler memory barrier:
   // twiddle loads cannot be hoisted out of the transform and held live
   // across unrelated work.
   gptr<const cx<T>> twp = tw;
   asm volatile("" : "+s"(twp) : : "memory");
   StageSeeds<DIR, T, N, RMAX, 0> none;   // stage 0 has no twiddles
-  fft_stages<DIR, T, N, RMAX, 0>(v, lre, lim, t, twp, none);
+  fft_stages<DIR, T, N, RMAX, 0, DB, X0>(v, xb, t, twp, none);
+}
+
+// Three transforms in a chain (one barrier in front when double-buffered).
+template <int DIR, typename T, int N, int RMAX, bool DB>
+__device__ __forceinline__ void fft3(cx<T> (&a)[RMAX], cx<T> (&b)[RMAX], cx<T> (&c)[RMAX], T* xb,
+                                     int t, gptr<const cx<T>> tw) {
+  constexpr int E = fft_exchanges<N, RMAX>();
+  if constexpr (DB) __syncthreads();
+  fft<DIR, T, N, RMAX, DB, 0>(a, xb, t, tw);
+  fft<DIR, T, N, RMAX, DB, E>(b, xb, t, tw);
+  fft<DIR, T, N, RMAX, DB, 2 * E>(c, xb, t, tw);
 }
 
 }  // namespace pm

@@ -58,6 +58,9 @@
 #ifndef PM_COL_LDS_SKEW
 #define PM_COL_LDS_SKEW 16    // words between the FFT buffers of a block's columns, beyond their size
 #endif
+#ifndef PM_LDS_DB
+#define PM_LDS_DB 1   // double-buffered FFT exchanges where the LDS share allows
+#endif
 #ifndef PM_COL_WPE
 #define PM_COL_WPE 2
 #endif
@@ -229,20 +232,52 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// Blocks of `waves` waves that share a CU when each SIMD holds WPE waves,
+// and the LDS bytes each of them may take.
+constexpr int blocks_per_cu(int waves, int wpe) {
+  const int cu = 4 * wpe > waves ? 4 * wpe : waves;
+  return cu / waves > 1 ? cu / waves : 1;
+}
+constexpr size_t lds_budget(int waves, int wpe) {
+  return (size_t)160 * 1024 / blocks_per_cu(waves, wpe) - 2048;
+}
+constexpr size_t zmax(size_t a, size_t b) { return a > b ? a : b; }
+// Two exchange buffers stay within about one 64 KiB LDS immediate-offset
+// range of one base register; beyond it every access needs its own address
+// register and the kernels spill.
+template <typename T, int L>
+constexpr bool lds_db_near() {
+  return (size_t)3 * LdsSize<L>::value * sizeof(T) < 65536;
+}
+
 // LDS of one row-pass block.  One region serves in turn as the stage of one
 // row of each team's pair (HBM <-> LDS copies in 16-byte units), as the FFT
 // exchange buffers and as the per-thread sums of the pointwise step; the
-// phases are separated by block barriers.  Rows are staged when the region
-// still leaves room for two blocks per CU.
+// phases are separated by block barriers.  Rows are staged, and the
+// exchanges double-buffered, when the region still fits the LDS share of a
+// block at the CU's expected number of blocks.
 template <typename T, int L, int TEAMS, int TPF>
 struct RowLds {
+  static constexpr size_t budget = lds_budget((TEAMS * TPF + 63) / 64, PM_ROW_WPE);
   static constexpr size_t stage = (size_t)TEAMS * (L / 2) * 3 * sizeof(cx<T>);
-  static constexpr size_t fftb = (size_t)TEAMS * 2 * LdsSize<L>::value * sizeof(T);
+  static constexpr size_t fftb = (size_t)TEAMS * 2 * LdsSize<L>::value * sizeof(T);   // one buffer per team
   static constexpr size_t sums = (size_t)NSUM * TEAMS * TPF * sizeof(T);
-  static constexpr size_t base = fftb > sums ? fftb : sums;
-  static constexpr size_t with_stage = stage > base ? stage : base;
-  static constexpr bool staged = with_stage <= 78 * 1024;
-  static constexpr size_t bytes = staged ? with_stage : base;
+  static constexpr bool staged = zmax(stage, zmax(fftb, sums)) <= 78 * 1024;
+  static constexpr bool db = PM_LDS_DB && lds_db_near<T, L>() &&
+                             zmax(staged ? stage : 0, zmax(2 * fftb, sums)) <= budget;
+  static constexpr int team_words = (db ? 4 : 2) * LdsSize<L>::value;   // FFT buffers of one team
+  static constexpr size_t bytes = zmax(staged ? stage : 0, zmax(db ? 2 * fftb : fftb, sums));
+};
+
+// LDS of one column-pass block: the FFT buffers of each of its CB columns,
+// skewed by PM_COL_LDS_SKEW words; double-buffered when that fits.
+template <typename T, int L, int CB, int TPF>
+struct ColLds {
+  static constexpr size_t budget = lds_budget((CB * TPF + 63) / 64, PM_COL_WPE);
+  static constexpr bool db = PM_LDS_DB && lds_db_near<T, L>() &&
+                             (size_t)CB * (4 * LdsSize<L>::value + PM_COL_LDS_SKEW) * sizeof(T) <= budget;
+  static constexpr int col_words = (db ? 4 : 2) * LdsSize<L>::value + PM_COL_LDS_SKEW;
+  static constexpr size_t bytes = (size_t)CB * col_words * sizeof(T);
 };
 
 // A row pair's view of the half spectrum: bins m1 of rows (ra + r), r = 0, 1,
@@ -420,7 +455,9 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   constexpr int LOAD_GROUP = RMAX >= 4 ? 4 : RMAX;   // unrolled iterations whose loads may be in flight together
   constexpr bool LOADS_SPEC = MODE == ROW_ITER || MODE == ROW_INV || MODE == ROW_EMIT;
   constexpr bool POINTWISE = MODE == ROW_ITER || MODE == ROW_INIT;
-  constexpr bool STAGED = RowLds<T, L, TEAMS, TPF>::staged;
+  using RL = RowLds<T, L, TEAMS, TPF>;
+  constexpr bool STAGED = RL::staged;
+  constexpr bool DB = RL::db;
   constexpr int GSTRIDE = L * WT * 3, SSTRIDE = WT * 3;
   constexpr int BPS = (L / 2) / TEAMS;                 // blocks per slot
   const Slot<T>& S = slots[blockIdx.x / BPS];
@@ -429,7 +466,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   const int team = threadIdx.x / TPF;
   const int t = threadIdx.x % TPF;
   // one LDS region, used in turn as row stage, FFT buffers and sums
-  T* lre = reinterpret_cast<T*>(smem_raw) + team * 2 * LS;
+  T* lre = reinterpret_cast<T*>(smem_raw) + team * RL::team_words;
   T* lim = lre + LS;
   cx<T>* stg = reinterpret_cast<cx<T>*>(smem_raw) + team * (L / 2) * 3;
   const int p = xcd_remap(blockIdx.x % BPS, BPS) * TEAMS + team;
@@ -509,9 +546,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       build(gbase, std::integral_constant<int, GSTRIDE>{});
     }
     fence(za); fence(zb); fence(zc);
-    fft<+1, T, L, RMAX>(za, lre, lim, t, tw);
-    fft<+1, T, L, RMAX>(zb, lre, lim, t, tw);
-    fft<+1, T, L, RMAX>(zc, lre, lim, t, tw);
+    fft3<+1, T, L, RMAX, DB>(za, zb, zc, lre, t, tw);
     fence(za); fence(zb); fence(zc);
   }
 
@@ -640,9 +675,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
     block_reduce_store<NSUM>(accd, glb(S.part) + (size_t)(blockIdx.x % BPS) * NPART);
   }
 
-  fft<-1, T, L, RMAX>(za, lre, lim, t, tw);
-  fft<-1, T, L, RMAX>(zb, lre, lim, t, tw);
-  fft<-1, T, L, RMAX>(zc, lre, lim, t, tw);
+  fft3<-1, T, L, RMAX, DB>(za, zb, zc, lre, t, tw);
 
   // Za -> (11, 22) of row a, Zb -> (11, 22) of row b, Zc -> 12 of rows a, b.
   constexpr int H = RMAX / 2;
@@ -786,8 +819,8 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
   // words so those accesses fall in different banks.
   const int wb = threadIdx.x % CB;        // column within the block
   const int t = threadIdx.x / CB;
-  T* lre = reinterpret_cast<T*>(smem_raw) + wb * (2 * LS + PM_COL_LDS_SKEW);
-  T* lim = lre + LS;
+  using CL = ColLds<T, L, CB, TPF>;
+  T* const lre = reinterpret_cast<T*>(smem_raw) + wb * CL::col_words;
   const int g = xcd_remap(blockIdx.x % BPS, BPS);
   const int m1 = g * CB + wb;
   const int w = m1 % W;                   // column within its tile
@@ -804,8 +837,7 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
     v[0][s] = ldc(q); v[1][s] = ldc(q + 1); v[2][s] = ldc(q + 2);
   }
   if constexpr ((MODE & COL_FWD) != 0) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) fft<-1, T, L, RMAX>(v[c], lre, lim, t, tw);
+    fft3<-1, T, L, RMAX, CL::db>(v[0], v[1], v[2], lre, t, tw);
   }
   if constexpr ((MODE & COL_GREEN) != 0) {
     const T lam0 = (T)S.prm.lam0, mu0 = (T)S.prm.mu0, scale = (T)x.scale;
@@ -853,8 +885,7 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
     }
   }
   if constexpr ((MODE & COL_INV) != 0) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) fft<+1, T, L, RMAX>(v[c], lre, lim, t, tw);
+    fft3<+1, T, L, RMAX, CL::db>(v[0], v[1], v[2], lre, t, tw);
   }
 #pragma unroll
   for (int s = 0; s < RMAX; ++s) {
@@ -921,7 +952,8 @@ static size_t row_lds() {
 }
 template <typename T, int L, int V>
 static size_t col_lds() {
-  return (size_t)Cfg<T, L, V>::COL_CB * (2 * LdsSize<L>::value + PM_COL_LDS_SKEW) * sizeof(T);
+  using C = Cfg<T, L, V>;
+  return ColLds<T, L, C::COL_CB, C::COL_TPF>::bytes;
 }
 
 template <typename T, int L, int V, int MODE>
