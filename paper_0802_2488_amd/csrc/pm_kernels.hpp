@@ -262,7 +262,7 @@ struct RowLds {
   static constexpr size_t stage = (size_t)TEAMS * (L / 2) * 3 * sizeof(cx<T>);
   static constexpr size_t fftb = (size_t)TEAMS * 2 * LdsSize<L>::value * sizeof(T);   // one buffer per team
   static constexpr size_t sums = (size_t)NSUM * TEAMS * TPF * sizeof(T);
-  static constexpr bool staged = zmax(stage, zmax(fftb, sums)) <= 78 * 1024;
+  static constexpr bool staged = zmax(stage, zmax(fftb, sums)) <= budget;
   static constexpr bool db = PM_LDS_DB && lds_db_near<T, L>() &&
                              zmax(staged ? stage : 0, zmax(2 * fftb, sums)) <= budget;
   static constexpr int team_words = (db ? 4 : 2) * LdsSize<L>::value;   // FFT buffers of one team
