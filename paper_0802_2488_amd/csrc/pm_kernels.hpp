@@ -58,6 +58,9 @@
 #ifndef PM_COL_LDS_SKEW
 #define PM_COL_LDS_SKEW 16    // words between the FFT buffers of a block's columns, beyond their size
 #endif
+#ifndef PM_COL_PAIRV
+#define PM_COL_PAIRV 1   // 16-byte accesses for FP32 column pairs
+#endif
 #ifndef PM_LDS_DB
 #define PM_LDS_DB 1   // double-buffered FFT exchanges where the LDS share allows
 #endif
@@ -829,12 +832,28 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
   gptr<cx<T>> __restrict__ tile = glb(S.spec) + (size_t)(m1 / W) * L * W * 3;
   gptr<cx<T>> __restrict__ xbuf = glb(S.xbuf);
 
+  // FP32 tiles of two columns, one per lane of a pair: the pair's six
+  // complex values of row m2 are 48 contiguous bytes.  Each lane moves its
+  // own 16-byte end and the middle 16 bytes (read by both, written as two
+  // 8-byte halves), two accesses per row instead of three 8-byte ones.
+  constexpr bool PAIRV = PM_COL_PAIRV && sizeof(T) == 4 && W == 2 && CB == 2;
+  using f4 = float __attribute__((ext_vector_type(4)));
   cx<T> v[3][RMAX];
 #pragma unroll
   for (int s = 0; s < RMAX; ++s) {
     const int m2 = t + TPF * s;
-    gptr<const cx<T>> q = tile + ((unsigned)m2 * W + w) * 3u;
-    v[0][s] = ldc(q); v[1][s] = ldc(q + 1); v[2][s] = ldc(q + 2);
+    if constexpr (PAIRV) {
+      gptr<const f4> row = (gptr<const f4>)(tile + (unsigned)m2 * 6u);
+      const f4 a = row[w ? 2 : 0];
+      const f4 b = row[1];
+      v[0][s] = w ? cx<T>{b.z, b.w} : cx<T>{a.x, a.y};
+      v[1][s] = w ? cx<T>{a.x, a.y} : cx<T>{a.z, a.w};
+      v[2][s] = w ? cx<T>{a.z, a.w} : cx<T>{b.x, b.y};
+      if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bounds the loads in flight
+    } else {
+      gptr<const cx<T>> q = tile + ((unsigned)m2 * W + w) * 3u;
+      v[0][s] = ldc(q); v[1][s] = ldc(q + 1); v[2][s] = ldc(q + 2);
+    }
   }
   if constexpr ((MODE & COL_FWD) != 0) {
     fft3<-1, T, L, RMAX, CL::db>(v[0], v[1], v[2], lre, t, tw);
@@ -887,11 +906,25 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
   if constexpr ((MODE & COL_INV) != 0) {
     fft3<+1, T, L, RMAX, CL::db>(v[0], v[1], v[2], lre, t, tw);
   }
+  // Opaque copies of the lane's indices: the store addresses are recomputed
+  // here instead of being held in registers from the loads.
+  int ts = t, ws = w;
+  asm volatile("" : "+v"(ts), "+v"(ws));
 #pragma unroll
   for (int s = 0; s < RMAX; ++s) {
-    const int m2 = t + TPF * s;
-    gptr<cx<T>> q = tile + ((unsigned)m2 * W + w) * 3u;
-    stc(q, v[0][s]); stc(q + 1, v[1][s]); stc(q + 2, v[2][s]);
+    const int m2 = ts + TPF * s;
+    const int w = ws;
+    if constexpr (PAIRV) {
+      // lane 0: (c0, c1) at bytes 0-15, c2 at 16-23; lane 1: c0 at 24-31, (c1, c2) at 32-47
+      const cx<T> p0 = w ? v[1][s] : v[0][s], p1 = w ? v[2][s] : v[1][s], q1 = w ? v[0][s] : v[2][s];
+      gptr<f4> row = (gptr<f4>)(tile + (unsigned)m2 * 6u);
+      row[w ? 2 : 0] = f4{p0.re, p0.im, p1.re, p1.im};
+      stc(tile + (unsigned)m2 * 6u + (w ? 3u : 2u), q1);
+      if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    } else {
+      gptr<cx<T>> q = tile + ((unsigned)m2 * W + w) * 3u;
+      stc(q, v[0][s]); stc(q + 1, v[1][s]); stc(q + 2, v[2][s]);
+    }
   }
 }
 
