@@ -348,6 +348,14 @@ __device__ __forceinline__ cx<T> load_bin(P base, int m, int r, int c) {
   return cconj(ldc(base + pidx<WT, TSTRIDE>(L - m, r, c)));
 }
 
+// An opaque copy of an index: addresses derived from it in one phase of a
+// kernel are recomputed in the next instead of being held in registers
+// across the phases in between.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Largest divisor of n that is at most cap.
 constexpr int divisor_upto(int n, int cap) {
   int d = cap < n ? cap : n;
@@ -489,10 +497,10 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   constexpr int PF = PM_ROW_PREFETCH < RMAX ? PM_ROW_PREFETCH : RMAX;
   T so[RMAX][2][4];
   uint8_t mk[RMAX][2];
-  auto fetch = [&](int s) {
+  auto fetch = [&](int s, int tt) {
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      const unsigned ix = (unsigned)(half ? rb : ra) * L + t + TPF * s;
+      const unsigned ix = (unsigned)(half ? rb : ra) * L + tt + TPF * s;
       mk[s][half] = mask[ix];
       if constexpr (MODE == ROW_ITER) {
 #pragma unroll
@@ -502,7 +510,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   };
   if constexpr (POINTWISE) {
 #pragma unroll
-    for (int s = 0; s < PF; ++s) fetch(s);
+    for (int s = 0; s < PF; ++s) fetch(s, t);
   }
 
   if constexpr (LOADS_SPEC) {
@@ -549,7 +557,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       build(gbase, std::integral_constant<int, GSTRIDE>{});
     }
     fence(za); fence(zb); fence(zc);
-    fft3<+1, T, L, RMAX, DB>(za, zb, zc, lre, t, tw);
+    fft3<+1, T, L, RMAX, DB>(za, zb, zc, lre, opaque(t), tw);
     fence(za); fence(zb); fence(zc);
   }
 
@@ -631,10 +639,11 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
     }
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) lacc[i][threadIdx.x] = (T)0;
+    const int tp = opaque(t);
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
-      const int x1 = t + TPF * s;
-      if (s + PF < RMAX) fetch(s + PF);
+      const int x1 = tp + TPF * s;
+      if (s + PF < RMAX) fetch(s + PF, tp);
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
@@ -678,27 +687,28 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
     block_reduce_store<NSUM>(accd, glb(S.part) + (size_t)(blockIdx.x % BPS) * NPART);
   }
 
-  fft3<-1, T, L, RMAX, DB>(za, zb, zc, lre, t, tw);
+  fft3<-1, T, L, RMAX, DB>(za, zb, zc, lre, opaque(t), tw);
 
   // Za -> (11, 22) of row a, Zb -> (11, 22) of row b, Zc -> 12 of rows a, b.
   constexpr int H = RMAX / 2;
   cx<T> xa[H], ya[H], xb[H], yb[H], xc[H], yc[H];
-  split_regs<T, L, RMAX>(za, lre, lim, t, xa, ya);
-  split_regs<T, L, RMAX>(zb, lre, lim, t, xb, yb);
-  split_regs<T, L, RMAX>(zc, lre, lim, t, xc, yc);
+  const int ts = opaque(t);
+  split_regs<T, L, RMAX>(za, lre, lim, ts, xa, ya);
+  split_regs<T, L, RMAX>(zb, lre, lim, ts, xb, yb);
+  split_regs<T, L, RMAX>(zc, lre, lim, ts, xc, yc);
   if constexpr (STAGED) {
     __syncthreads();
-    put_row<T, L, H, WT, SSTRIDE>(stg, t, 0, xa, ya, xc);
+    put_row<T, L, H, WT, SSTRIDE>(stg, ts, 0, xa, ya, xc);
     __syncthreads();
     typename RowUnits<T, L, WT, TPF>::u4 hold[RowUnits<T, L, WT, TPF>::PER];
-    stage_to_hold<T, L, WT, TPF>(stg, t, hold);
+    stage_to_hold<T, L, WT, TPF>(stg, ts, hold);
     __syncthreads();
-    put_row<T, L, H, WT, SSTRIDE>(stg, t, 0, xb, yb, yc);
+    put_row<T, L, H, WT, SSTRIDE>(stg, ts, 0, xb, yb, yc);
     __syncthreads();
-    stage_pair_out<T, L, WT, TPF>(gbase, stg, t, hold);
+    stage_pair_out<T, L, WT, TPF>(gbase, stg, opaque(t), hold);
   } else {
-    put_row<T, L, H, WT, GSTRIDE>(gbase, t, 0, xa, ya, xc);
-    put_row<T, L, H, WT, GSTRIDE>(gbase, t, 1, xb, yb, yc);
+    put_row<T, L, H, WT, GSTRIDE>(gbase, ts, 0, xa, ya, xc);
+    put_row<T, L, H, WT, GSTRIDE>(gbase, ts, 1, xb, yb, yc);
   }
 }
 
