@@ -38,7 +38,10 @@
 #define PM_ROW_WPE 2          // minimum waves per SIMD requested for the row pass
 #endif
 #ifndef PM_ROW_PREFETCH
-#define PM_ROW_PREFETCH 1     // pixel pairs of stress fetched ahead in the row pass
+#define PM_ROW_PREFETCH 2     // pixel pairs of stress fetched ahead in the FP32 row pass
+#endif
+#ifndef PM_ROW_PREFETCH64
+#define PM_ROW_PREFETCH64 1   // the same for FP64 (twice the registers per pair)
 #endif
 #ifndef PM_STAGE_INFLIGHT
 #define PM_STAGE_INFLIGHT 6   // 16-byte loads per thread in flight while staging a row
@@ -485,7 +488,9 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   gptr<cx<T>> __restrict__ gbase = glb(S.spec) + (size_t)ra * WT * 3;
   gptr<const cx<T>> __restrict__ tw = glb(S.tw);
   gptr<const uint8_t> __restrict__ mask = glb(S.mask);
-  gptr<T> __restrict__ sig = glb(S.sig);
+  // the stress state: (11, 22, 33, 12) of a pixel side by side, one vector
+  using v4 = T __attribute__((ext_vector_type(4)));
+  gptr<v4> __restrict__ sig = (gptr<v4>)glb(S.sig);
   const Mat<T> m = make_mat<T>(S.prm);
   constexpr unsigned NPX = (unsigned)L * L;
 
@@ -494,7 +499,8 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   // Stress and mask of the thread's pixel pairs, fetched PF pairs ahead of
   // the pointwise step; the first PF pairs are issued before the inverse
   // transforms so they arrive while those run.
-  constexpr int PF = PM_ROW_PREFETCH < RMAX ? PM_ROW_PREFETCH : RMAX;
+  constexpr int PF_WANT = sizeof(T) == 4 ? PM_ROW_PREFETCH : PM_ROW_PREFETCH64;
+  constexpr int PF = PF_WANT < RMAX ? PF_WANT : RMAX;
   T so[RMAX][2][4];
   uint8_t mk[RMAX][2];
   auto fetch = [&](int s, int tt) {
@@ -503,8 +509,8 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       const unsigned ix = (unsigned)(half ? rb : ra) * L + tt + TPF * s;
       mk[s][half] = mask[ix];
       if constexpr (MODE == ROW_ITER) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) so[s][half][c] = sig[c * NPX + ix];
+        const v4 q = sig[ix];
+        so[s][half][0] = q.x; so[s][half][1] = q.y; so[s][half][2] = q.z; so[s][half][3] = q.w;
       }
     }
   };
@@ -590,7 +596,8 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
         T tau[3];
         if (half == 0) { tau[0] = za[s].re * invL; tau[1] = za[s].im * invL; tau[2] = zc[s].re * invL; }
         else { tau[0] = zb[s].re * invL; tau[1] = zb[s].im * invL; tau[2] = zc[s].im * invL; }
-        T sg[4] = {sig[ix], sig[NPX + ix], sig[2 * NPX + ix], sig[3 * NPX + ix]};
+        const v4 q = sig[ix];
+        T sg[4] = {q.x, q.y, q.z, q.w};
         T en[4];
         strain_from(sg, tau, isv, m, en);
         T dummy[4];
@@ -667,7 +674,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
           else { e[0] = zb[s].re; e[1] = zb[s].im; e[2] = zc[s].im; }
           pl = alm_point(e, so[s][half], isv, m, en, sg, tau);
         }
-        sig[ix] = sg[0]; sig[NPX + ix] = sg[1]; sig[2 * NPX + ix] = sg[2]; sig[3 * NPX + ix] = sg[3];
+        sig[ix] = v4{sg[0], sg[1], sg[2], sg[3]};
         {
           const T c0 = e[0] - en[0], c1 = e[1] - en[1], c2 = en[2], c3 = e[2] - en[3];
           const T v6[NSUM] = {sg[0], sg[1], sg[2], sg[3], c0 * c0 + c1 * c1 + c2 * c2 + (T)2 * c3 * c3,

@@ -117,17 +117,18 @@ __global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, 
   gptr<const DevState> st = glb(S.st);
   if (!force && (st->halted || !st->need_eq)) return;
   const long npx = (long)L * L;
-  gptr<const T> __restrict__ s11 = glb(S.sig);
-  gptr<const T> __restrict__ s22 = s11 + npx;
-  gptr<const T> __restrict__ s12 = s11 + 3 * npx;
+  // stress state: (11, 22, 33, 12) per pixel
+  using v4 = T __attribute__((ext_vector_type(4)));
+  gptr<const v4> __restrict__ sg = (gptr<const v4>)glb(S.sig);
   double acc[1] = {0.0};
   for (long ix = (long)lb * blockDim.x + threadIdx.x; ix < npx; ix += (long)dbps * blockDim.x) {
     const int x1 = (int)(ix & (L - 1));
     const int x2 = (int)(ix / L);
     const long i1 = (long)x2 * L + ((x1 + L - 1) & (L - 1));   // x - e^1
     const long i2 = (long)((x2 + L - 1) & (L - 1)) * L + x1;   // x - e^2
-    const double d1 = ((double)s11[ix] - (double)s11[i1]) + ((double)s12[ix] - (double)s12[i2]);
-    const double d2 = ((double)s12[ix] - (double)s12[i1]) + ((double)s22[ix] - (double)s22[i2]);
+    const v4 a = sg[ix], b1 = sg[i1], b2 = sg[i2];
+    const double d1 = ((double)a.x - (double)b1.x) + ((double)a.w - (double)b2.w);
+    const double d2 = ((double)a.w - (double)b1.w) + ((double)a.y - (double)b2.y);
     acc[0] += d1 * d1 + d2 * d2;
   }
   block_reduce_store<1>(acc, glb(S.part2) + lb);

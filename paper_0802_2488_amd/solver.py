@@ -115,8 +115,9 @@ class Solver:
 
     # -- kernel-level hooks -------------------------------------------------
     def buffers(self):
-        """Views of the workspace: the stress state (4, L, L) and the raw half
-        spectrum (L*L/2*3*2,) in the tiled layout of pm_spectrum_tile."""
+        """Views of the workspace: the stress state (L, L, 4), components
+        (11, 22, 33, 12) of a pixel side by side, and the raw half spectrum
+        (L*L/2*3*2,) in the tiled layout of pm_spectrum_tile."""
         e = ctypes.c_void_p()
         s = ctypes.c_void_p()
         check(lib().pm_solver_buffers(self.handle, ctypes.byref(e), ctypes.byref(s)), "pm_solver_buffers")
@@ -126,7 +127,7 @@ class Solver:
         eo = (e.value - base) // es
         so = (s.value - base) // es
         flat = self.workspace.view(self.dtype)
-        eps_t = flat[eo: eo + 4 * L * L].view(4, L, L)
+        eps_t = flat[eo: eo + 4 * L * L].view(L, L, 4)
         spec_t = flat[so: so + L * (L // 2) * 6]
         return eps_t, spec_t
 

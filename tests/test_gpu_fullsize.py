@@ -3,7 +3,8 @@ times (FP32 fields, FP64 norms, default kernels).
 
 L = 1024 (the curve-and-masks workload) and L = 4096 (the benchmark
 workload) are compared with the FP64 oracle iteration-locked over a few
-iterations of their first load steps.  At L = 8192, the largest size the
+iterations of their first load steps, in FP32 (<= 1e-4) and in FP64
+(<= 1e-10).  At L = 8192, the largest size the
 library accepts, the checks are properties that hold at any size: exact
 uniform fields in a homogeneous medium, zero stress in voids and the Mises
 cap, and FP32 against the library's own FP64 path (which the smaller-size
@@ -38,22 +39,32 @@ def params(L, precision, max_iter, tol=0.0):
 
 
 @pytest.mark.parametrize("L,f,kind,steps,iters", [(1024, 0.2, "equibiaxial", 2, 4), (4096, 0.3, "shear", 1, 2)])
-def test_workload_sizes_iteration_locked_fp32(L, f, kind, steps, iters):
+def test_workload_sizes_iteration_locked(L, f, kind, steps, iters):
+    """FP32 (the benchmark's precision) and FP64 against one oracle run."""
     mask = synth.bernoulli_mask(L, f, 0)
     nsteps = 50 if L == 1024 else 40
     path = synth.load_path(kind, nsteps, synth.default_emax(kind, 1.0, 1.0))[:steps]
-    g = pms.Solver(torch.tensor(mask, device="cuda"), params(L, "fp32", iters))
+    tm = torch.tensor(mask, device="cuda")
+    g32 = pms.Solver(tm, params(L, "fp32", iters))
+    g64 = pms.Solver(tm, params(L, "fp64", iters))
     o = alm.Solver(mask, alm.Params(L=L))
     for E in path:
-        rg = g.step(E)
         ro = o.step(E, fixed_iters=iters)
+        rg = g32.step(E)
         assert rg.iters == iters
         assert rel(t33(rg.sigma), ro.sigma) <= 1e-4
         band = np.abs(ro.margin) <= 1e-5
         assert np.array_equal(rg.plastic.cpu().numpy().astype(bool)[~band], ro.plastic[~band])
         np.testing.assert_allclose(rg.sigma_mean, alm.voigt4(ro.sigma_mean), rtol=1e-4, atol=1e-6)
-        del ro
-    g.close()
+        del rg
+        rd = g64.step(E)
+        assert rd.iters == iters
+        assert rel(t33(rd.sigma), ro.sigma) <= 1e-10
+        assert rel(t33(rd.eps), ro.eps) <= 1e-10
+        np.testing.assert_array_equal(rd.plastic.cpu().numpy().astype(bool)[~band], ro.plastic[~band])
+        del rd, ro
+    g32.close()
+    g64.close()
 
 
 def test_max_size_homogeneous_medium_exact():

@@ -278,7 +278,7 @@ def test_noconv_and_nan_paths():
     r = g.step((0.3, 0.3, 0.0))
     assert r.status == -4 and r.iters == 1 and not r.converged
     eps, _ = g.buffers()
-    eps[0, 3, 5] = float("nan")
+    eps[3, 5, 0] = float("nan")
     r = g.step((0.3, 0.3, 0.0))
     assert r.status == -5 and not r.converged
 
