@@ -319,3 +319,20 @@ def test_five_point_average_matches_oracle(L, precision, tol):
     torch.cuda.synchronize()
     ref = np.moveaxis(dg.five_point_average(np.moveaxis(xin.cpu().double().numpy(), 0, -1)), -1, 0)
     assert np.abs(out.cpu().double().numpy() - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("L,precision", [(4096, "fp32"), (256, "fp64")])
+def test_mask_at_any_byte_offset(L, precision):
+    """The solver borrows the caller's mask; one that starts at an odd byte
+    (a view into a larger buffer) gives the same results bit for bit."""
+    mask = synth.bernoulli_mask(L, 0.3, 4)
+    flat = torch.zeros(L * L + 16, dtype=torch.uint8, device="cuda")
+    flat[1:1 + L * L] = torch.tensor(mask.ravel(), device="cuda")
+    odd = flat[1:1 + L * L].view(L, L)
+    assert odd.data_ptr() % 16 == 1
+    E = (0.0, 0.0, 0.05)
+    p = gpu_params(L, precision, tol=0.0, max_iter=3)
+    ra = pms.Solver(torch.tensor(mask, device="cuda"), p).step(E)
+    rb = pms.Solver(odd, p).step(E)
+    assert torch.equal(ra.sigma, rb.sigma) and torch.equal(ra.eps, rb.eps)
+    assert torch.equal(ra.plastic, rb.plastic)
