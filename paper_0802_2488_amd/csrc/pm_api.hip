@@ -118,7 +118,7 @@ struct pm_solver {
   hipStream_t stream;
   int device;
   char* ws;
-  void* sig;       // state: stress of the last iterate (4 planes)
+  void* sig;       // state: stress of the last iterate, 4 components per pixel
   void* spec;
   DevState* st;
   void* slot;      // device table of one pm::Slot<T>

@@ -11,8 +11,9 @@
 //   reductions  : fixed-order FP64 sums, convergence indicators, and the
 //                 backward-difference equilibrium residual when the other two
 //                 indicators already pass                      (k_reduce*, k_div)
-// The persistent state is the stress of the last iterate (4 planes: 11, 22,
-// 33, 12), which is also the augmented-Lagrangian multiplier, and the half
+// The persistent state is the stress of the last iterate ((11, 22, 33, 12)
+// of each pixel side by side), which is also the augmented-Lagrangian
+// multiplier, and the half
 // spectrum of the polarisation tau; the strain is recovered from both when
 // outputs are written.
 #pragma once
