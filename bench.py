@@ -34,13 +34,19 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_L4096_fp32_shear.md")
 
 
 def kernel_sources_digest() -> str:
-    """SHA-256 over the sources of the FP32 row and column kernels."""
+    """SHA-256 over the code of the FP32 row and column kernels' sources:
+    comments and blank space are dropped first, so editing a comment does
+    not retire counter figures taken from the same code."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_0802_2488_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_0802_2488_amd", "csrc", name), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)   # block comments
+        text = re.sub(r"//[^\n]*", " ", text)                  # line comments
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 
