@@ -48,6 +48,7 @@ struct DevState {
   int32_t pending;             // a step ended; its record waits for the output pass
   int32_t hold;                // wait after every step until the host resumes the slot
   int32_t held;                // waiting (step ended, record complete, next step not begun)
+  uint32_t div_ticket;         // blocks of the residual pass done (0 between passes)
 };
 
 struct DevParams {
@@ -62,7 +63,7 @@ struct DevParams {
 template <typename T>
 struct Slot {
   cx<T>* spec;           // half spectrum (tiled, packed)
-  T* sig;                // state: stress of the last iterate (= multiplier), 4 planes
+  T* sig;                // state: stress of the last iterate (= multiplier), 4 components per pixel
   const uint8_t* mask;   // 1 = void
   double* part;          // per-block partial sums of the row pass (NPART each)
   double* part2;         // residual and output-pass partial sums

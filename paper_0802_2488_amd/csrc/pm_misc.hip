@@ -19,6 +19,7 @@ __device__ __forceinline__ void begin_step(P st, double E0, double E1, double E2
   st->floor_s = 1e-12 * mu * st->normE;
   st->iter = 0; st->halted = 0; st->status = ST_RUNNING; st->need_eq = 0;
   st->res_eq = st->res_mac = st->res_cmp = INFINITY;
+  st->div_ticket = 0;
 }
 
 // A load step ended with `status`.  The slot halts.  Without a device ramp
@@ -109,12 +110,19 @@ __global__ void __launch_bounds__(256) k_reduce(const Slot<T>* __restrict__ slot
 }
 
 // Backward-difference divergence of eq. 1 of the stored stress:
-// div_i(x) = sum_j sigma_ij(x) - sigma_ij(x - e^j), direction 1 = x1.
+// div_i(x) = sum_j sigma_ij(x) - sigma_ij(x - e^j), direction 1 = x1, and
+// from it the equilibrium indicator eta_1, which ends the step on
+// convergence or at max_iter.  Each block stores its partial sum; the last
+// block of a slot to finish (a ticket in the slot state, taken after a
+// device-scope fence that publishes the partial) adds the partials in index
+// order and decides.  Blocks return at once unless the indicator is needed,
+// so the fences only run in the iterations that evaluate it.  force: only
+// record the indicator.
 template <typename T>
 __global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, int L, int dbps, int force) {
   const Slot<T>& S = slots[blockIdx.x / dbps];
   const int lb = blockIdx.x % dbps;
-  gptr<const DevState> st = glb(S.st);
+  gptr<DevState> st = glb(S.st);
   if (!force && (st->halted || !st->need_eq)) return;
   const long npx = (long)L * L;
   // stress state: (11, 22, 33, 12) per pixel
@@ -131,21 +139,19 @@ __global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, 
     const double d2 = ((double)a.w - (double)b1.w) + ((double)a.y - (double)b2.y);
     acc[0] += d1 * d1 + d2 * d2;
   }
-  block_reduce_store<1>(acc, glb(S.part2) + lb);
-}
-
-// Equilibrium indicator eta_1 from the residual partials; ends the step on
-// convergence or at max_iter.  force: only record the indicator.
-template <typename T>
-__global__ void __launch_bounds__(256) k_reduce_div(const Slot<T>* __restrict__ slots, int nblk, int force) {
-  const Slot<T>& S = slots[blockIdx.x];
-  gptr<DevState> st = glb(S.st);
-  if (!force && (st->halted || !st->need_eq)) return;
+  gptr<double> part2 = glb(S.part2);
+  block_reduce_store<1>(acc, part2 + lb);   // thread 0 stores the block's partial
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(&S.st->div_ticket, 1u) == (unsigned)dbps - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
   __shared__ double red[256];
   double s = 0.0;
-  gptr<const double> part2 = glb(S.part2);
-#pragma unroll 4
-  for (int b = threadIdx.x; b < nblk; b += 256) s += part2[b];
+  for (int b = threadIdx.x; b < dbps; b += 256) s += part2[b];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
@@ -153,6 +159,7 @@ __global__ void __launch_bounds__(256) k_reduce_div(const Slot<T>* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    st->div_ticket = 0;
     const double ns = fmax(norm4(st->sm), st->floor_s);
     const double req = sqrt(red[0] / S.prm.npx) / ns;
     st->res_eq = req;
@@ -278,7 +285,7 @@ uint64_t tuning_generation() { return g_tune_gen.load(std::memory_order_relaxed)
 int div_blocks(int L) {
   const long npx = (long)L * L;
   long g = (npx + 255) / 256;
-  if (g > 1024) g = 1024;
+  if (g > 256) g = 256;   // one block per CU; the pass is rarely needed and exits at once otherwise
   return (int)g;
 }
 
@@ -292,9 +299,6 @@ template <typename T>
 hipError_t launch_div(const Slot<T>* slots, int nslots, int L, int force, hipStream_t s) {
   const int g = div_blocks(L);
   hipLaunchKernelGGL(k_div<T>, dim3(nslots * g), dim3(256), 0, s, slots, L, g, force);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_div<T>, dim3(nslots), dim3(256), 0, s, slots, g, force);
   return hipGetLastError();
 }
 
