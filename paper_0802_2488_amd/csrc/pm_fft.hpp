@@ -198,7 +198,7 @@ struct Plan {
   static constexpr int ns(int i) { return i == 0 ? 1 : ns(i - 1) * radix(i - 1); }
 };
 
-// LDS index with one padding word every 16 words (breaks power-of-two strides).
+// LDS index with one padding element every 16 (breaks power-of-two strides).
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 template <int N>
 struct LdsSize {
@@ -276,8 +276,9 @@ __device__ __forceinline__ void apply_seeds(cx<T>* u, const cx<T> (&sd)[4]) {
 }
 
 // LDS exchange buffers of one transform team, from a base pointer: buffer
-// b holds real parts at base + 2 b S and imaginary parts at base + (2 b + 1) S,
-// S = LdsSize<N>::value.  With one buffer a stage's writes wait at a barrier
+// b holds S = LdsSize<N>::value complex values (real and imaginary part
+// side by side, one LDS access each) at base + 2 b S.  With one buffer a
+// stage's writes wait at a barrier
 // until every thread has read the previous stage; with two (DB),
 // consecutive exchanges alternate between the buffers, so only the barrier
 // between an exchange's writes and its reads remains.
@@ -308,7 +309,7 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__
       } else {
         const int j = t + b * TPF;
         const int idx = lpad(j + r * (N / R));
-        u[b * R + r] = {xb[2 * RD * S + idx], xb[(2 * RD + 1) * S + idx]};
+        u[b * R + r] = reinterpret_cast<const cx<T>*>(xb + 2 * RD * S)[idx];
       }
     }
   }
@@ -324,18 +325,13 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[RMAX], T* __restrict__
       for (int r = 0; r < R; ++r) v[b + B * r] = u[b * R + r];
   } else {
     if constexpr (!DB) __syncthreads();
-    T* __restrict__ wre = xb + 2 * WR * S;
-    T* __restrict__ wim = xb + (2 * WR + 1) * S;
+    cx<T>* __restrict__ wb = reinterpret_cast<cx<T>*>(xb + 2 * WR * S);
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = t + b * TPF;
       const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int idx = lpad(base + r * NS);
-        wre[idx] = u[b * R + r].re;
-        wim[idx] = u[b * R + r].im;
-      }
+      for (int r = 0; r < R; ++r) wb[lpad(base + r * NS)] = u[b * R + r];
     }
     __syncthreads();
   }

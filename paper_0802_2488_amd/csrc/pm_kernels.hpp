@@ -301,30 +301,25 @@ __device__ __forceinline__ unsigned pidx(int m1, int r, int c) {
 // m < L/2, with the real Nyquist values packed into the imaginary slots of
 // bin 0.  Thread t gets bins m = t + TPF k, k < RMAX / 2.
 template <typename T, int L, int RMAX>
-__device__ __forceinline__ void split_regs(const cx<T> (&z)[RMAX], T* lre, T* lim, int t, cx<T> (&X)[RMAX / 2],
+__device__ __forceinline__ void split_regs(const cx<T> (&z)[RMAX], cx<T>* lz, int t, cx<T> (&X)[RMAX / 2],
                                            cx<T> (&Y)[RMAX / 2]) {
   constexpr int TPF = L / RMAX;
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < RMAX; ++s) {
-    const int idx = lpad(t + TPF * s);
-    lre[idx] = z[s].re;
-    lim[idx] = z[s].im;
-  }
+  for (int s = 0; s < RMAX; ++s) lz[lpad(t + TPF * s)] = z[s];
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < RMAX / 2; ++k) {
     const int mm = t + TPF * k;
-    const int i0 = lpad(mm), i1 = lpad((L - mm) & (L - 1));
-    const cx<T> zm = {lre[i0], lim[i0]};
-    const cx<T> zr = {lre[i1], -lim[i1]};   // conj Z[L - m]
+    const cx<T> zm = lz[lpad(mm)];
+    const cx<T> zr = cconj(lz[lpad((L - mm) & (L - 1))]);   // conj Z[L - m]
     const cx<T> d = zm - zr;
     X[k] = cscale(zm + zr, (T)0.5);
     Y[k] = {d.im * (T)0.5, -d.re * (T)0.5};
     if (mm == 0) {
-      const int ih = lpad(L / 2);
-      X[k].im = lre[ih];   // Re Z[L/2]: Nyquist bin of x
-      Y[k].im = lim[ih];   // Im Z[L/2]: Nyquist bin of y
+      const cx<T> zh = lz[lpad(L / 2)];
+      X[k].im = zh.re;   // Re Z[L/2]: Nyquist bin of x
+      Y[k].im = zh.im;   // Im Z[L/2]: Nyquist bin of y
     }
   }
 }
@@ -482,7 +477,6 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   const int t = threadIdx.x % TPF;
   // one LDS region, used in turn as row stage, FFT buffers and sums
   T* lre = reinterpret_cast<T*>(smem_raw) + team * RL::team_words;
-  T* lim = lre + LS;
   cx<T>* stg = reinterpret_cast<cx<T>*>(smem_raw) + team * (L / 2) * 3;
   const int p = xcd_remap(blockIdx.x % BPS, BPS) * TEAMS + team;
   const int ra = 2 * p, rb = 2 * p + 1;
@@ -701,9 +695,10 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   constexpr int H = RMAX / 2;
   cx<T> xa[H], ya[H], xb[H], yb[H], xc[H], yc[H];
   const int ts = opaque(t);
-  split_regs<T, L, RMAX>(za, lre, lim, ts, xa, ya);
-  split_regs<T, L, RMAX>(zb, lre, lim, ts, xb, yb);
-  split_regs<T, L, RMAX>(zc, lre, lim, ts, xc, yc);
+  cx<T>* lz = reinterpret_cast<cx<T>*>(lre);
+  split_regs<T, L, RMAX>(za, lz, ts, xa, ya);
+  split_regs<T, L, RMAX>(zb, lz, ts, xb, yb);
+  split_regs<T, L, RMAX>(zc, lz, ts, xc, yc);
   if constexpr (STAGED) {
     __syncthreads();
     put_row<T, L, H, WT, SSTRIDE>(stg, ts, 0, xa, ya, xc);
