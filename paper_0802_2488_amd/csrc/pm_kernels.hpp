@@ -270,7 +270,10 @@ struct RowLds {
   static constexpr size_t fftb = (size_t)TEAMS * 2 * LdsSize<L>::value * sizeof(T);   // one buffer per team
   static constexpr size_t sums = (size_t)NSUM * TEAMS * TPF * sizeof(T);
   static constexpr bool staged = zmax(stage, zmax(fftb, sums)) <= budget;
-  static constexpr bool db = PM_LDS_DB && lds_db_near<T, L>() &&
+  // FP64 row passes take two buffers wherever they fit (no spills at the
+  // sizes where they do: L = 4096 at 228 VGPRs); FP32 ones only within the
+  // offset range (L = 8192 spills otherwise)
+  static constexpr bool db = PM_LDS_DB && (sizeof(T) == 8 || lds_db_near<T, L>()) &&
                              zmax(staged ? stage : 0, zmax(2 * fftb, sums)) <= budget;
   static constexpr int team_words = (db ? 4 : 2) * LdsSize<L>::value;   // FFT buffers of one team
   static constexpr size_t bytes = zmax(staged ? stage : 0, zmax(db ? 2 * fftb : fftb, sums));
