@@ -110,11 +110,13 @@ def algorithmic_bytes(L: int, fs: int):
     """Compulsory HBM bytes per launch of the row and column passes.
 
     Half spectrum: L rows x (L/2 + 1) momenta x 3 complex values.
-    Row pass: read + write the spectrum, read + write eps (4 planes), read mask.
+    Row pass: read + write the spectrum, read + write the stress state
+    (4 components per pixel; it also carries the void flag, so the
+    iteration pass does not read the mask).
     Column pass: read + write the spectrum.
     """
     spec = L * (L // 2 + 1) * 3 * 2 * fs
-    row = 2 * spec + 2 * 4 * L * L * fs + L * L
+    row = 2 * spec + 2 * 4 * L * L * fs
     col = 2 * spec
     return row, col
 

@@ -195,7 +195,9 @@ int32_t pm_spectrum_tile(int32_t L, int32_t precision);
  * pm_solver_buffers   device pointers of the solver state and of the half
  *                     spectrum.  The state is the stress of the last iterate,
  *                     (11, 22, 33, 12) of each pixel side by side, pixels
- *                     x2-major; it is also the augmented-Lagrangian
+ *                     x2-major (a void's stress is zero, its 33 component a
+ *                     negative zero, which marks the void for the iteration
+ *                     pass; outputs carry +0); it is also the augmented-Lagrangian
  *                     multiplier; the strain is recovered from it and the
  *                     stored polarisation when outputs are written.
  * pm_debug_forward    d_real: 3 planes (11, 22, 12).  Spectrum := the 2-D

@@ -97,6 +97,20 @@ __device__ __forceinline__ Mat<T> make_mat(const DevParams& p) {
   return m;
 }
 
+// The stored stress of a void is exactly zero; its 33 component is kept as
+// a negative zero, which marks the pixel as a void for the iteration pass
+// (so that pass does not read the mask).  Matrix pixels store their 33
+// component plus +0, which turns a negative zero into a positive one and
+// leaves every other value unchanged.
+__device__ __forceinline__ bool void_flagged(float v) { return __float_as_uint(v) == 0x80000000u; }
+__device__ __forceinline__ bool void_flagged(double v) {
+  return (unsigned long long)__double_as_longlong(v) == 0x8000000000000000ull;
+}
+template <typename T>
+__device__ __forceinline__ T flag33(T s33, bool is_void) {
+  return is_void ? -(T)0 : s33 + (T)0;
+}
+
 // 1 / sqrt(x): the hardware estimate in FP32 (~1 ulp), exact in FP64.
 __device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
@@ -505,7 +519,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const unsigned ix = (unsigned)(half ? rb : ra) * L + tt + TPF * s;
-      mk[s][half] = mask[ix];
+      if constexpr (MODE != ROW_ITER) mk[s][half] = mask[ix];
       if constexpr (MODE == ROW_ITER) {
         const v4 q = sig[ix];
         so[s][half][0] = q.x; so[s][half][1] = q.y; so[s][half][2] = q.z; so[s][half][3] = q.w;
@@ -604,7 +618,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
         for (int c = 0; c < 4; ++c) acc[c] += (double)en[c];
         if (sig_out) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) sig_out[c * NPX + ix] = sg[c];
+          for (int c = 0; c < 4; ++c) sig_out[c * NPX + ix] = sg[c] + (T)0;   // the void flag's -0 as +0
         }
         if (eps_out) {
 #pragma unroll
@@ -652,7 +666,11 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const unsigned ix = (unsigned)(half ? rb : ra) * L + x1;
-        const bool isv = mk[s][half] != 0;
+        // iterations read the void flag from the state (a negative zero in
+        // the 33 component, see void_flagged) instead of the mask
+        bool isv;
+        if constexpr (MODE == ROW_ITER) isv = void_flagged(so[s][half][2]);
+        else isv = mk[s][half] != 0;
         T e[3], en[4], sg[4], tau[3];
         bool pl = false;
         if constexpr (MODE == ROW_INIT) {
@@ -672,7 +690,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
           else { e[0] = zb[s].re; e[1] = zb[s].im; e[2] = zc[s].im; }
           pl = alm_point(e, so[s][half], isv, m, en, sg, tau);
         }
-        sig[ix] = v4{sg[0], sg[1], sg[2], sg[3]};
+        sig[ix] = v4{sg[0], sg[1], flag33(sg[2], isv), sg[3]};
         {
           const T c0 = e[0] - en[0], c1 = e[1] - en[1], c2 = en[2], c3 = e[2] - en[3];
           const T v6[NSUM] = {sg[0], sg[1], sg[2], sg[3], c0 * c0 + c1 * c1 + c2 * c2 + (T)2 * c3 * c3,
