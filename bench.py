@@ -405,7 +405,8 @@ def main():
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the solve is per-GPU; see the sharding notes in DESIGN.md)"}))
+                                   "(independent solves shard by placing whole realizations on different GPUs, "
+                                   "one process each)"}))
         sys.exit(2)
     import torch
 
