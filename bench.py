@@ -404,7 +404,7 @@ def main():
         copy_reference()
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
                                    "(independent solves shard by placing whole realizations on different GPUs, "
                                    "one process each)"}))
         sys.exit(2)
