@@ -336,3 +336,22 @@ def test_mask_at_any_byte_offset(L, precision):
     rb = pms.Solver(odd, p).step(E)
     assert torch.equal(ra.sigma, rb.sigma) and torch.equal(ra.eps, rb.eps)
     assert torch.equal(ra.plastic, rb.plastic)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_void_flag_in_state_and_positive_zero_outputs(precision):
+    """The stored stress marks voids by a negative zero in its 33 component
+    (the iteration pass reads no mask); outputs give voids +0 stress."""
+    L = 64
+    mask = synth.bernoulli_mask(L, 0.3, 9)
+    g = pms.Solver(torch.tensor(mask, device="cuda"), gpu_params(L, precision, tol=0.0, max_iter=5))
+    r = g.step((0.2, -0.1, 0.15))
+    void = torch.tensor(mask.astype(bool), device="cuda")
+    state, _ = g.buffers()
+    s33 = state[..., 2]
+    flagged = (s33 == 0) & torch.signbit(s33)
+    assert torch.equal(flagged, void)
+    assert float(state[void].abs().max()) == 0.0
+    assert not bool(torch.signbit(r.sigma[:, void]).any())
+    assert float(r.sigma[:, void].abs().max()) == 0.0
+    g.close()
