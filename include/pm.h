@@ -140,7 +140,10 @@ size_t pm_workspace_bytes(const pm_params* params);
  *   out          receives the handle (host memory).
  *   params       copied; see pm_params.
  *   d_void_mask  device uint8 L*L, 1 = void (Sec. 2, pixels are voids with
- *                concentration f), borrowed until pm_solver_destroy.
+ *                concentration f), any alignment, borrowed until
+ *                pm_solver_destroy and not to be changed meanwhile (the state
+ *                written from it on the first step keeps the void flags the
+ *                iterations use).
  *   d_workspace  device memory of at least pm_workspace_bytes(params),
  *                256-byte aligned, borrowed until pm_solver_destroy.
  *   stream       hipStream_t for all work of this solver.
