@@ -238,10 +238,12 @@ typedef struct pm_kernel_timing {
 } pm_kernel_timing;
 
 /*
- * enable = 1 resets the totals and starts timing; 0 stops it.  While timing
- * is on the host waits for each group of check_every iterations before
- * issuing the next (no overlap of host polling with device work).  out (may
- * be NULL) receives the totals accumulated so far.
+ * enable = n >= 1 resets the totals and starts timing every n-th iteration
+ * (events around its launches; each event pair costs device time, so a
+ * sampled n keeps the timed run close to an untimed one); 0 stops timing.
+ * Host polling stays pipelined: a chunk's events are read once its state
+ * has come back.  out (may be NULL) receives the totals accumulated so far.
+ * Errors: PM_EINVAL (NULL solver, enable < 0), PM_EDEVICE.
  */
 int pm_solver_timing(pm_solver* solver, int32_t enable, pm_kernel_timing* out);
 int pm_debug_forward(pm_solver* solver, const void* d_real);

@@ -126,9 +126,10 @@ struct pm_solver {
   hipEvent_t ev[2];
   bool started;
   int chunk;
-  // opt-in per-kernel timing
-  bool timing;
-  std::vector<hipEvent_t> tev;   // 4 events per iteration of one chunk
+  // opt-in per-kernel timing of every timing_every-th iteration
+  bool timing = false;
+  int timing_every = 1;
+  std::vector<hipEvent_t> tev;   // 4 events per iteration of a chunk, for both chunk slots
   pm_kernel_timing tacc;
 };
 
@@ -160,11 +161,13 @@ int green_kind(const pm_params& q) {
 }
 
 template <typename T>
-int iterate_once(pm_solver* s, int slot_in_chunk) {
+int iterate_once(pm_solver* s, int slot_in_chunk, int chunk_slot = 0) {
   const int L = s->p.L;
   const pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_RUNNING, 1.0 / ((double)L * (double)L), nullptr);
   const pm::Slot<T>* S = dslot<T>(s);
-  hipEvent_t* ev = s->timing ? &s->tev[4 * slot_in_chunk] : nullptr;
+  hipEvent_t* ev = s->timing && slot_in_chunk % s->timing_every == 0
+                      ? &s->tev[4 * ((size_t)chunk_slot * s->chunk + slot_in_chunk)]
+                      : nullptr;
   if (ev) PM_HIP(hipEventRecord(ev[0], s->stream));
   const pm::Tuning tv = pm::get_tuning(s->p.precision, L);
   PM_HIP(pm::launch_col<T>(L, pm::col_mode(pm::COL_ALL, green_kind(s->p)), tv.col, S, 1, x, s->stream));
@@ -177,13 +180,15 @@ int iterate_once(pm_solver* s, int slot_in_chunk) {
   return PM_OK;
 }
 
-// Add the event times of the first `executed` iterations of a finished chunk.
-int collect_timing(pm_solver* s, int executed) {
-  for (int i = 0; i < executed; ++i) {
+// Add the event times of the timed iterations among the first `executed` of
+// a finished chunk (iterations after the device halted did no work).
+int collect_timing(pm_solver* s, int chunk_slot, int executed) {
+  for (int i = 0; i < executed; i += s->timing_every) {
+    const hipEvent_t* e = &s->tev[4 * ((size_t)chunk_slot * s->chunk + i)];
     float a = 0.f, b = 0.f, c = 0.f;
-    PM_HIP(hipEventElapsedTime(&a, s->tev[4 * i], s->tev[4 * i + 1]));
-    PM_HIP(hipEventElapsedTime(&b, s->tev[4 * i + 1], s->tev[4 * i + 2]));
-    PM_HIP(hipEventElapsedTime(&c, s->tev[4 * i + 2], s->tev[4 * i + 3]));
+    PM_HIP(hipEventElapsedTime(&a, e[0], e[1]));
+    PM_HIP(hipEventElapsedTime(&b, e[1], e[2]));
+    PM_HIP(hipEventElapsedTime(&c, e[2], e[3]));
     s->tacc.col_ms += a;
     s->tacc.row_ms += b;
     s->tacc.other_ms += c;
@@ -247,30 +252,28 @@ int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
   }
   PM_HIP(pm::launch_begin(s->st, E, s->p.mu, 0, 1, 0, s->stream));
   const int max_iter = s->p.max_iter;
+  // Pipelined: the next chunk is queued before the previous chunk's state is
+  // read.  With timing on, a chunk's events are read once its state is back;
+  // the state's iteration count says how many of its iterations did work.
   int issued = 0, slot = 0, pend = -1, fin = -1;
-  while (fin < 0 && s->timing) {
-    // timed mode: one chunk at a time so each chunk's executed iterations are known
-    const int n = std::min(s->chunk, max_iter - issued);
-    for (int i = 0; i < n; ++i) {
-      int rc = iterate_once<T>(s, i);
+  int chunk_n[2] = {0, 0};
+  int done_iter = 0;   // iteration count at the end of the last chunk read back
+  auto finish_chunk = [&](int c) -> int {
+    if (s->timing) {
+      int rc = collect_timing(s, c, std::min(chunk_n[c], s->hst[c].iter - done_iter));
       if (rc != PM_OK) return rc;
     }
-    const int before = issued == 0 ? 0 : s->hst[0].iter;
-    issued += n;
-    PM_HIP(hipMemcpyAsync(&s->hst[0], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
-    PM_HIP(hipStreamSynchronize(s->stream));
-    int rc = collect_timing(s, std::min(n, s->hst[0].iter - before));
-    if (rc != PM_OK) return rc;
-    if (s->hst[0].halted || issued >= max_iter) fin = 0;
-  }
+    done_iter = s->hst[c].iter;
+    return PM_OK;
+  };
   while (fin < 0) {
-    // pipelined: the next chunk is queued before the previous chunk's state is read
     if (issued < max_iter) {
       const int n = std::min(s->chunk, max_iter - issued);
       for (int i = 0; i < n; ++i) {
-        int rc = iterate_once<T>(s, i);
+        int rc = iterate_once<T>(s, i, slot);
         if (rc != PM_OK) return rc;
       }
+      chunk_n[slot] = n;
       issued += n;
       PM_HIP(hipMemcpyAsync(&s->hst[slot], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
       PM_HIP(hipEventRecord(s->ev[slot], s->stream));
@@ -279,10 +282,14 @@ int step_impl(pm_solver* s, const double* E, pm_step_out* out) {
       slot ^= 1;
       if (prev >= 0) {
         PM_HIP(hipEventSynchronize(s->ev[prev]));
+        int rc = finish_chunk(prev);
+        if (rc != PM_OK) return rc;
         if (s->hst[prev].halted) fin = prev;
       }
     } else {
       PM_HIP(hipEventSynchronize(s->ev[pend]));
+      int rc = finish_chunk(pend);
+      if (rc != PM_OK) return rc;
       fin = pend;
     }
   }
@@ -442,13 +449,15 @@ int pm_solver_destroy(pm_solver* s) {
 
 int pm_solver_timing(pm_solver* s, int32_t enable, pm_kernel_timing* out) {
   if (!s) return fail(PM_EINVAL, "solver is NULL");
+  if (enable < 0) return fail(PM_EINVAL, "enable must be >= 0");
   if (enable) {
     if (s->tev.empty()) {
-      s->tev.resize(4 * (size_t)s->chunk, nullptr);
+      s->tev.resize(2 * 4 * (size_t)s->chunk, nullptr);
       for (auto& e : s->tev) PM_HIP(hipEventCreate(&e));
     }
     s->tacc = pm_kernel_timing{};
     s->timing = true;
+    s->timing_every = enable;
   } else {
     s->timing = false;
   }

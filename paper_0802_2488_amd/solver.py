@@ -107,10 +107,11 @@ class Solver:
         return StepResult(np.array(out.sigma_mean[:]), np.array(out.eps_mean[:]), out.res_eq, out.res_mac,
                           out.res_cmp, out.iters, bool(out.converged), rc, sig, eps, pl)
 
-    def timing(self, enable: bool):
-        """Start (resetting totals) or stop per-kernel event timing; returns the totals."""
+    def timing(self, enable: bool, every: int = 1):
+        """Start (resetting totals) or stop per-kernel event timing of every
+        `every`-th iteration; returns the totals."""
         t = _lib.PmKernelTiming()
-        check(lib().pm_solver_timing(self.handle, 1 if enable else 0, ctypes.byref(t)), "pm_solver_timing")
+        check(lib().pm_solver_timing(self.handle, int(every) if enable else 0, ctypes.byref(t)), "pm_solver_timing")
         return {k: getattr(t, k) for k, _ in t._fields_}
 
     # -- kernel-level hooks -------------------------------------------------

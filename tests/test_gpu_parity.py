@@ -355,3 +355,27 @@ def test_void_flag_in_state_and_positive_zero_outputs(precision):
     assert not bool(torch.signbit(r.sigma[:, void]).any())
     assert float(r.sigma[:, void].abs().max()) == 0.0
     g.close()
+
+
+def test_kernel_timing_all_or_every_nth_iteration():
+    """Event timing of every iteration or of every n-th one: counts of the
+    timed launches, and the same solve bit for bit as without timing."""
+    L = 256
+    mask = synth.bernoulli_mask(L, 0.2, 5)
+    p = gpu_params(L, "fp32", tol=0.0, max_iter=40)
+    E = (0.1, 0.05, 0.02)
+    ref = pms.Solver(torch.tensor(mask, device="cuda"), p).step(E)
+    g = pms.Solver(torch.tensor(mask, device="cuda"), p)
+    g.timing(True, every=1)
+    r1 = g.step(E)
+    t1 = g.timing(False)
+    assert torch.equal(r1.sigma, ref.sigma) and torch.equal(r1.eps, ref.eps)
+    assert t1["iterations"] == t1["row_launches"] == t1["col_launches"] == r1.iters == 40
+    assert t1["row_ms"] > 0 and t1["col_ms"] > 0 and t1["other_ms"] > 0
+    g.timing(True, every=4)
+    r2 = g.step(E)
+    t2 = g.timing(False)
+    assert r2.iters == 40
+    chunk = 128   # the default chunk at L = 256 holds all 40 iterations
+    assert t2["iterations"] == len(range(0, min(40, chunk), 4))
+    assert 0.5 < (t2["row_ms"] / t2["row_launches"]) / (t1["row_ms"] / t1["row_launches"]) < 2.0
