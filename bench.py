@@ -354,25 +354,73 @@ def next_rows_section(plastic_4096=None):
     # equilibrium DG1 and CG1 do not solve; methods are compared by the
     # iterations until the change and constraint indicators pass.
     L = 128
-    m = pms.device_mask(L, 0.1, 0)
     E1 = synth.load_path("equibiaxial", 10, 3.0)[0]
-    its = {}
-    for name, v in (("DG eq.3", 0), ("DG1", 4), ("CG1", 5)):
+    geoms = {"bernoulli f=0.1 (seed 0)": pms.device_mask(L, 0.1, 0),
+             "one circular void f=0.1": torch.tensor(synth.circular_void(L, 0.1), device="cuda")}
+    methods = {}
+    for gname, m in geoms.items():
+        its = {}
+        for name, v in (("DG eq.3", 0), ("DG1", 4), ("CG1", 5)):
+            q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.5, lam0=1.0, tol=1e-6, eta_eq=1e30,
+                                max_iter=4000, precision="fp64", green_variant=v)
+            s = pms.Solver(m, q)
+            r = s.step(E1, fields=False)
+            its[name] = {"iters": r.iters, "converged": r.converged, "res_eq_backward_difference": r.res_eq}
+            s.close()
         q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.5, lam0=1.0, tol=1e-6, eta_eq=1e30, max_iter=4000,
-                            precision="fp64", green_variant=v)
-        s = pms.Solver(m, q)
-        r = s.step(E1, fields=False)
-        its[name] = {"iters": r.iters, "converged": r.converged, "res_eq_backward_difference": r.res_eq}
-        s.close()
-    q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.5, lam0=1.0, tol=1e-6, eta_eq=1e30, max_iter=4000,
-                        precision="fp64")
-    st = dg2.solve_path(m, q, [E1], fields=False)[0]
-    its["DG2"] = {"iters_per_variant": [r.iters for r in st.records],
-                  "converged": all(r.status == 1 for r in st.records)}
-    out["method_iterations"] = {"workload": f"L={L}, f=0.1, equibiaxial load step 1 of 10, reference medium "
-                                            "0.5x matrix, change and constraint indicators < 1e-6, FP64, "
-                                            "max_iter 4000", **its}
+                            precision="fp64")
+        st = dg2.solve_path(m, q, [E1], fields=False)[0]
+        its["DG2"] = {"iters_per_variant": [r.iters for r in st.records],
+                      "converged": all(r.status == 1 for r in st.records)}
+        methods[gname] = its
+    out["method_iterations"] = {"workload": f"L={L}, equibiaxial load step 1 of 10, reference medium 0.5x "
+                                            "matrix, change and constraint indicators < 1e-6, FP64, max_iter 4000",
+                                **methods}
+    print("# methods done", file=sys.stderr, flush=True)
+    out["cluster_path"] = cluster_path()
+    print("# cluster path done", file=sys.stderr, flush=True)
     return out
+
+
+def cluster_path(L=1024, f=0.2, nsteps=50, max_iter=200):
+    """Sec. 3 indicators along the curve-and-masks workload: per load step the
+    cluster counts of the plastic mask, eps0 = <(eps11 + eps22) / 2>,
+    sigma0 = <(sigma11 + sigma22) / 2>, and from them r = dn/d eps0 and
+    -d2 sigma0 / d eps0^2 (library finite differences)."""
+    import torch
+
+    from paper_0802_2488_amd import clusters
+    from paper_0802_2488_amd import solver as pms
+    from paper_0802_2488_amd import synth
+
+    vm = pms.device_mask(L, f, 0)
+    path = synth.load_path("equibiaxial", nsteps, synth.default_emax("equibiaxial", 1.0, 1.0))
+    p = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=1e-6, max_iter=max_iter, precision="fp32")
+    s = pms.Solver(vm, p)
+    eps0, sig0, n, vmax, spans, iters = [], [], [], [], [], []
+    t0 = time.perf_counter()
+    for E in path:
+        r = s.step(E)
+        _, st = clusters.analyze(vm, r.plastic)
+        ind = clusters.indicators(st, L)
+        eps0.append(0.5 * (r.eps_mean[0] + r.eps_mean[1]))
+        sig0.append(0.5 * (r.sigma_mean[0] + r.sigma_mean[1]))
+        n.append(ind["n"])
+        vmax.append(ind["v_max"])
+        spans.append(bool(st["spans_x1"] and st["spans_x2"]))
+        iters.append(r.iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.close()
+    pi = clusters.path_indicators(np.array(eps0), np.array(n), np.array(sig0))
+    k = int(np.argmax(pi["r"]))
+    return {"workload": f"L={L}, f={f} (seed 0), equibiaxial, {nsteps} load steps to 3Y/mu, tol 1e-6, FP32, "
+                        f"max_iter {max_iter}; clusters of every step's plastic mask",
+            "seconds": dt, "iters_per_step": iters,
+            "eps0": eps0, "sigma0": sig0, "n": n, "v_max": vmax,
+            "r": pi["r"].tolist(), "minus_d2sigma0": pi["minus_d2sigma0"].tolist(),
+            "eps0_at_max_r": eps0[k],
+            "eps0_first_spanning": next((e for e, sp in zip(eps0, spans) if sp), None)}
 
 
 def cpu_baseline(L):

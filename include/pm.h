@@ -428,6 +428,15 @@ size_t pm_cluster_workspace_bytes(int32_t L);
 int pm_clusters(int32_t L, const uint8_t* d_void_mask, const uint8_t* d_plastic, int32_t* d_labels,
                 void* d_workspace, size_t workspace_bytes, pm_cluster_stats* out, void* stream);
 
+/* Loading-path indicators of Sec. 3 (r = dn/d eps0, and -d2 sigma0/d eps0^2
+ * from the mean stress curve): first and second derivatives of samples
+ * y[k] taken at strictly increasing x[k], k < n_steps, by three-point
+ * finite differences on the non-uniform grid (central inside, one-sided at
+ * the ends; exact for quadratics).  All arrays are host memory of n_steps
+ * doubles; dy or d2y may be NULL.  Errors: PM_EINVAL (n_steps < 3, NULL x
+ * or y, x not strictly increasing or not finite). */
+int pm_path_derivatives(int32_t n_steps, const double* x, const double* y, double* dy, double* d2y);
+
 
 /* CG2 (Sec. 2): the average of a field over each pixel and its four nearest
  * neighbours (periodic), applied plane by plane.  d_in, d_out: device,

@@ -171,3 +171,32 @@ def indicators(stats, L, f=None):
     nvc = max(stats["n_void_clusters"], 1)
     return dict(v_p=vp, f_p=vp / (1.0 - f), v_max=stats["largest"] / npx,
                 i=stats["n_isolated_void_clusters"] / nvc, n=stats["n_clusters"] / nvc)
+
+
+def path_derivatives(x, y):
+    """First and second derivatives along a loading path (Sec. 3: r = dn/d eps0
+    and the curvature -d2 sigma0 / d eps0^2 of the mean stress curve).  Each
+    point takes the quadratic through three consecutive samples (its own and
+    its neighbours; the first or last three at the ends) and differentiates
+    it: a local fit with numpy.polyfit, not a difference formula."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = len(x)
+    assert n >= 3 and np.all(np.diff(x) > 0)
+    dy = np.empty(n)
+    d2y = np.empty(n)
+    for k in range(n):
+        c = min(max(k, 1), n - 2)
+        xs, ys = x[c - 1:c + 2], y[c - 1:c + 2]
+        x0 = xs[1]                                   # centre the fit for conditioning
+        coef = np.polyfit(xs - x0, ys, 2)            # exact through the three points
+        dy[k] = np.polyval(np.polyder(coef), x[k] - x0)
+        d2y[k] = 2.0 * coef[0]
+    return dy, d2y
+
+
+def path_indicators(eps0, n, sigma0):
+    """r = dn/d eps0 and -d2 sigma0 / d eps0^2 at each step of a loading path."""
+    r, _ = path_derivatives(eps0, n)
+    _, s2 = path_derivatives(eps0, sigma0)
+    return dict(r=r, minus_d2sigma0=-s2)

@@ -129,6 +129,8 @@ SIGNATURES = [
     ("pm_clusters", ctypes.c_int,
      [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
       ctypes.POINTER(PmClusterStats), ctypes.c_void_p]),
+    ("pm_path_derivatives", ctypes.c_int,
+     [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("pm_five_point_average", ctypes.c_int,
      [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("pm_autotune_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
 import torch
 
 from ._lib import PmClusterStats, check, lib
@@ -48,3 +49,25 @@ def indicators(stats, L, f=None):
     nvc = max(stats["n_void_clusters"], 1)
     return dict(v_p=vp, f_p=vp / (1.0 - f), v_max=stats["largest"] / npx,
                 i=stats["n_isolated_void_clusters"] / nvc, n=stats["n_clusters"] / nvc)
+
+
+def path_derivatives(x, y):
+    """(dy/dx, d2y/dx2) of samples y at strictly increasing x (host arrays),
+    three-point finite differences computed by the library."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    if x.shape != y.shape or x.ndim != 1:
+        raise ValueError("x and y must be 1-D arrays of one length")
+    dy = np.empty_like(x)
+    d2y = np.empty_like(x)
+    check(lib().pm_path_derivatives(len(x), x.ctypes.data, y.ctypes.data, dy.ctypes.data, d2y.ctypes.data),
+          "pm_path_derivatives")
+    return dy, d2y
+
+
+def path_indicators(eps0, n, sigma0):
+    """Sec. 3 indicators along a loading path: r = dn/d eps0 and
+    -d2 sigma0 / d eps0^2 at each step."""
+    r, _ = path_derivatives(eps0, n)
+    _, s2 = path_derivatives(eps0, sigma0)
+    return dict(r=r, minus_d2sigma0=-s2)

@@ -303,6 +303,8 @@ hipError_t cc_span(int L, const int* lab, int root, int* cols, int* rows, unsign
 // ---------------------------------------------------------------------------
 // C ABI
 #include "pm.h"
+#include <cmath>
+
 #include "pm_host.hpp"
 
 namespace {
@@ -400,6 +402,38 @@ int pm_clusters(int32_t L, const uint8_t* d_void_mask, const uint8_t* d_plastic,
   out->largest_label = largest_root;
   out->spans_x1 = (largest_root >= 0 && h[8] == (unsigned long long)L) ? 1 : 0;
   out->spans_x2 = (largest_root >= 0 && h[9] == (unsigned long long)L) ? 1 : 0;
+  return PM_OK;
+}
+
+// Derivatives of the quadratic through three consecutive samples: with
+// h1 = x1 - x0 and h2 = x2 - x1 the weights of (y0, y1, y2) are, for the
+// slope at x0, x1, x2 and for the (constant) second derivative,
+//   x0: (-(2 h1 + h2) / (h1 (h1 + h2)),  (h1 + h2) / (h1 h2), -h1 / (h2 (h1 + h2)))
+//   x1: (-h2 / (h1 (h1 + h2)),  (h2 - h1) / (h1 h2),  h1 / (h2 (h1 + h2)))
+//   x2: ( h2 / (h1 (h1 + h2)), -(h1 + h2) / (h1 h2),  (h1 + 2 h2) / (h2 (h1 + h2)))
+//   y'': 2 (1 / (h1 (h1 + h2)), -1 / (h1 h2), 1 / (h2 (h1 + h2))).
+int pm_path_derivatives(int32_t n_steps, const double* x, const double* y, double* dy, double* d2y) {
+  using pmh::fail;
+  if (n_steps < 3) return fail(PM_EINVAL, "n_steps = %d: at least 3 samples are needed", n_steps);
+  if (!x || !y) return fail(PM_EINVAL, "x and y must be host arrays");
+  for (int k = 0; k < n_steps; ++k)
+    if (!std::isfinite(x[k]) || (k > 0 && !(x[k] > x[k - 1])))
+      return fail(PM_EINVAL, "x must be finite and strictly increasing (index %d)", k);
+  for (int k = 0; k < n_steps; ++k) {
+    // stencil k-1, k, k+1 inside; the first or last three samples at the ends
+    const int c = k == 0 ? 1 : (k == n_steps - 1 ? n_steps - 2 : k);
+    const double y0 = y[c - 1], y1 = y[c], y2 = y[c + 1];
+    const double h1 = x[c] - x[c - 1], h2 = x[c + 1] - x[c], hs = h1 + h2;
+    if (dy) {
+      if (k == c)
+        dy[k] = -h2 / (h1 * hs) * y0 + (h2 - h1) / (h1 * h2) * y1 + h1 / (h2 * hs) * y2;
+      else if (k < c)
+        dy[k] = -(2.0 * h1 + h2) / (h1 * hs) * y0 + hs / (h1 * h2) * y1 - h1 / (h2 * hs) * y2;
+      else
+        dy[k] = h2 / (h1 * hs) * y0 - hs / (h1 * h2) * y1 + (h1 + 2.0 * h2) / (h2 * hs) * y2;
+    }
+    if (d2y) d2y[k] = 2.0 * (y0 / (h1 * hs) - y1 / (h1 * h2) + y2 / (h2 * hs));
+  }
   return PM_OK;
 }
 

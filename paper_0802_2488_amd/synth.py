@@ -54,6 +54,15 @@ def bernoulli_mask(L: int, f: float, seed: int) -> np.ndarray:
     return (uniform01(seed, p) < f).astype(np.uint8).reshape(L, L)
 
 
+def circular_void(L: int, f: float) -> np.ndarray:
+    """One circular void of area fraction f centred in the periodic cell (the
+    single-inclusion cell of Sec. 2's method comparison): pixel (x1, x2) is a
+    void iff its centre lies within radius L sqrt(f / pi) of the cell centre."""
+    c = np.arange(L) + 0.5 - L / 2.0
+    r2 = c[None, :] ** 2 + c[:, None] ** 2
+    return (r2 < (L * L) * f / np.pi).astype(np.uint8)
+
+
 def load_path(kind: str, n_steps: int, e_max: float) -> np.ndarray:
     """(n_steps, 3) array of (E11, E22, E12); step n (1-based) applies n*e_max/N."""
     e = e_max * np.arange(1, n_steps + 1, dtype=np.float64) / n_steps

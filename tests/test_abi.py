@@ -83,3 +83,16 @@ def test_mask_porosity_statistics():
     assert abs(m.mean() - 0.3) < 4 * np.sqrt(0.3 * 0.7 / m.size)
     assert synth.bernoulli_mask(64, 0.0, 1).sum() == 0
     assert synth.bernoulli_mask(64, 1.0, 1).sum() == 64 * 64
+
+
+@pytest.mark.parametrize("L,f", [(64, 0.1), (128, 0.1), (256, 0.3)])
+def test_circular_void_cell(L, f):
+    m = synth.circular_void(L, f)
+    assert m.dtype == np.uint8 and m.shape == (L, L)
+    # area within the pixels crossed by the boundary circle
+    assert abs(int(m.sum()) - f * L * L) <= 2 * np.pi * L * np.sqrt(f / np.pi) + 4
+    # symmetric under both mirrors and the transpose of the cell
+    assert np.array_equal(m, m[::-1, :]) and np.array_equal(m, m[:, ::-1]) and np.array_equal(m, m.T)
+    # one 4-connected cluster
+    from scipy import ndimage
+    assert ndimage.label(m)[1] == 1

@@ -74,3 +74,18 @@ def test_invalid_size():
     with pytest.raises(ValueError):
         gc.analyze(torch.zeros((12, 12), dtype=torch.uint8, device="cuda"),
                    torch.zeros((12, 12), dtype=torch.uint8, device="cuda"))
+
+
+def test_path_derivatives_library_matches_oracle():
+    """Host function of the library against the oracle's local quadratic fits."""
+    rng = np.random.default_rng(11)
+    for n in (3, 4, 7, 50):
+        x = np.cumsum(rng.uniform(0.01, 1.0, n))
+        y = rng.normal(size=n)
+        dl, d2l = gc.path_derivatives(x, y)
+        do, d2o = oc.path_derivatives(x, y)
+        scale = np.abs(do).max() + 1.0
+        np.testing.assert_allclose(dl, do, rtol=0, atol=1e-9 * scale)
+        np.testing.assert_allclose(d2l, d2o, rtol=0, atol=1e-8 * (np.abs(d2o).max() + 1.0))
+    with pytest.raises(Exception):
+        gc.path_derivatives(np.array([0.0, 1.0, 1.0]), np.zeros(3))

@@ -108,3 +108,36 @@ def test_indicators_of_an_unloaded_grid():
     assert ind["i"] == 1.0 and ind["n"] == 1.0
     f = void.mean()
     assert ind["f_p"] == pytest.approx(f / (1 - f))
+
+
+def test_path_derivatives_exact_for_quadratics():
+    rng = np.random.default_rng(3)
+    x = np.cumsum(rng.uniform(0.05, 0.5, 12))
+    a, b, c = 0.4, -2.0, 1.5
+    dy, d2y = clusters.path_derivatives(x, a + b * x + c * x * x)
+    np.testing.assert_allclose(dy, b + 2 * c * x, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(d2y, 2 * c, rtol=0, atol=1e-9)
+
+
+def test_path_derivatives_uniform_grid_and_second_order():
+    # on a uniform grid the inner slope is the central difference
+    x = np.linspace(0.0, 1.0, 11)
+    y = np.exp(x)
+    dy, d2y = clusters.path_derivatives(x, y)
+    h = x[1] - x[0]
+    np.testing.assert_allclose(dy[1:-1], (y[2:] - y[:-2]) / (2 * h), rtol=1e-12)
+    np.testing.assert_allclose(d2y[1:-1], (y[2:] - 2 * y[1:-1] + y[:-2]) / h**2, rtol=1e-9)
+    # errors fall as h^2 inside (ratio ~4 when h halves)
+    errs = []
+    for m in (21, 41):
+        x = np.linspace(0.0, 1.0, m)
+        dy, _ = clusters.path_derivatives(x, np.sin(x))
+        errs.append(np.abs(dy[1:-1] - np.cos(x[1:-1])).max())
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_path_indicators_of_linear_curves():
+    eps0 = np.array([0.1, 0.25, 0.3, 0.5, 0.8])
+    ind = clusters.path_indicators(eps0, 2.0 - 0.5 * eps0, 3.0 * eps0 + 1.0)
+    np.testing.assert_allclose(ind["r"], -0.5, atol=1e-12)
+    np.testing.assert_allclose(ind["minus_d2sigma0"], 0.0, atol=1e-9)
