@@ -494,13 +494,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 fields, f64 norms",
+        "dtype": "f32",
         "data": "synthetic (seeded Bernoulli void mask)",
         "config": {"workload": f"single realization L={L}, f=0.3, simple shear to 4Y/mu over 40 load steps, "
                                f"tol 1e-6, FP32 fields + FP64 norms; step = one load step (max_iter "
                                f"{a.max_iter})",
                    "L": L, "f": 0.3, "seed": 0, "load_steps_timed": list(range(a.warmup + 1, a.warmup + a.steps + 1)),
-                   "parallelism": "1 GPU", "autotuned_variants": tuned},
+                   "reductions": "f64 partial sums and norms", "parallelism": "1 GPU",
+                   "autotuned_variants": tuned},
         "roofline": {"bound": "hbm", "kernel": "k_row (inverse row FFT + pointwise step + forward row FFT)",
                      "achieved": row_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": row_gbs / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic["k_row"],
