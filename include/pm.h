@@ -428,6 +428,27 @@ size_t pm_cluster_workspace_bytes(int32_t L);
 int pm_clusters(int32_t L, const uint8_t* d_void_mask, const uint8_t* d_plastic, int32_t* d_labels,
                 void* d_workspace, size_t workspace_bytes, pm_cluster_stats* out, void* stream);
 
+/* Per-step indicators of Sec. 3 (Fig. 2 legend) from the counts of one
+ * pm_clusters call on an L x L grid:
+ *   v_p   = (void + plastic pixels) / L^2, the void-plastic volume fraction;
+ *   f_p   = v_p / (1 - f), its normalised form, with f = void_fraction, or
+ *           the realised n_void / L^2 when void_fraction < 0;
+ *   v_max = pixels of the largest void-plastic cluster / L^2;
+ *   i     = void clusters holding no plastic pixel / void clusters (the
+ *           proportion of isolated voids);
+ *   n     = void-plastic clusters after the nearest-void attachment / void
+ *           clusters (at zero load every void-plastic cluster is a void
+ *           cluster, so n is normalised to its value there).
+ * With no void cluster, i and n divide by 1.  Host memory only; errors:
+ * PM_EINVAL (NULL pointer, L not a power of two in [4, PM_MAX_L], counts
+ * negative or beyond L^2, f >= 1). */
+typedef struct pm_cluster_indicators_out {
+  double v_p, f_p, v_max, i, n;
+} pm_cluster_indicators_out;
+
+int pm_cluster_indicators(const pm_cluster_stats* stats, int32_t L, double void_fraction,
+                          pm_cluster_indicators_out* out);
+
 /* Loading-path indicators of Sec. 3 (r = dn/d eps0, and -d2 sigma0/d eps0^2
  * from the mean stress curve): first and second derivatives of samples
  * y[k] taken at strictly increasing x[k], k < n_steps, by three-point

@@ -82,6 +82,11 @@ class PmClusterStats(ctypes.Structure):
     ]
 
 
+class PmClusterIndicators(ctypes.Structure):
+    _fields_ = [("v_p", ctypes.c_double), ("f_p", ctypes.c_double), ("v_max", ctypes.c_double),
+                ("i", ctypes.c_double), ("n", ctypes.c_double)]
+
+
 class PmDg2Out(ctypes.Structure):
     _fields_ = [
         ("eps", ctypes.c_void_p), ("sigma_of_avg", ctypes.c_void_p), ("sigma_avg", ctypes.c_void_p),
@@ -129,6 +134,8 @@ SIGNATURES = [
     ("pm_clusters", ctypes.c_int,
      [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
       ctypes.POINTER(PmClusterStats), ctypes.c_void_p]),
+    ("pm_cluster_indicators", ctypes.c_int,
+     [ctypes.POINTER(PmClusterStats), ctypes.c_int32, ctypes.c_double, ctypes.POINTER(PmClusterIndicators)]),
     ("pm_path_derivatives", ctypes.c_int,
      [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("pm_five_point_average", ctypes.c_int,

@@ -13,7 +13,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import PmClusterStats, check, lib
+from ._lib import PmClusterIndicators, PmClusterStats, check, lib
 
 
 def analyze(void_mask: torch.Tensor, plastic: torch.Tensor, stream=None):
@@ -42,13 +42,16 @@ def analyze(void_mask: torch.Tensor, plastic: torch.Tensor, stream=None):
 
 
 def indicators(stats, L, f=None):
-    """Sec. 3 indicators: v_p, f_p = v_p / (1 - f), v_max, i and n."""
-    npx = L * L
-    f = stats["n_void"] / npx if f is None else f
-    vp = (stats["n_void"] + stats["n_plastic"]) / npx
-    nvc = max(stats["n_void_clusters"], 1)
-    return dict(v_p=vp, f_p=vp / (1.0 - f), v_max=stats["largest"] / npx,
-                i=stats["n_isolated_void_clusters"] / nvc, n=stats["n_clusters"] / nvc)
+    """Sec. 3 indicators v_p, f_p, v_max, i and n, computed by the library
+    from the counts of ``analyze`` (f: the void fraction; None = realised)."""
+    st = PmClusterStats()
+    for k, _ in st._fields_:
+        if k != "pad":
+            setattr(st, k, int(stats[k]))
+    out = PmClusterIndicators()
+    check(lib().pm_cluster_indicators(ctypes.byref(st), int(L), -1.0 if f is None else float(f), ctypes.byref(out)),
+          "pm_cluster_indicators")
+    return {k: getattr(out, k) for k, _ in out._fields_}
 
 
 def path_derivatives(x, y):

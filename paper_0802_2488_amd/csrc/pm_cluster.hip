@@ -412,6 +412,34 @@ int pm_clusters(int32_t L, const uint8_t* d_void_mask, const uint8_t* d_plastic,
 //   x1: (-h2 / (h1 (h1 + h2)),  (h2 - h1) / (h1 h2),  h1 / (h2 (h1 + h2)))
 //   x2: ( h2 / (h1 (h1 + h2)), -(h1 + h2) / (h1 h2),  (h1 + 2 h2) / (h2 (h1 + h2)))
 //   y'': 2 (1 / (h1 (h1 + h2)), -1 / (h1 h2), 1 / (h2 (h1 + h2))).
+int pm_cluster_indicators(const pm_cluster_stats* stats, int32_t L, double void_fraction,
+                          pm_cluster_indicators_out* out) {
+  using pmh::fail;
+  if (!stats || !out) return fail(PM_EINVAL, "stats and out must be host pointers");
+  if (!pmh::is_pow2(L) || L < 4 || L > PM_MAX_L)
+    return fail(PM_EINVAL, "L = %d must be a power of two in [4, %d]", L, PM_MAX_L);
+  const int64_t npx = (int64_t)L * L;
+  const int64_t counts[] = {stats->n_void, stats->n_plastic, stats->n_void_clusters,
+                            stats->n_isolated_void_clusters, stats->n_clusters, stats->largest};
+  for (int64_t c : counts)
+    if (c < 0 || c > npx) return fail(PM_EINVAL, "cluster count %lld outside [0, L^2]", (long long)c);
+  if (stats->n_void + stats->n_plastic > npx)
+    return fail(PM_EINVAL, "void and plastic pixels exceed L^2");
+  const double area = (double)npx;
+  const double f = void_fraction < 0.0 ? (double)stats->n_void / area : void_fraction;
+  if (!(f < 1.0)) return fail(PM_EINVAL, "void fraction %g must be below 1", f);
+  // Sec. 3: the void-plastic phase is the voids together with the plastic
+  // zones; cluster counts are taken relative to the void clusters, which are
+  // all the clusters of that phase at zero load.
+  const double voids = stats->n_void_clusters > 0 ? (double)stats->n_void_clusters : 1.0;
+  out->v_p = (double)(stats->n_void + stats->n_plastic) / area;
+  out->f_p = out->v_p / (1.0 - f);
+  out->v_max = (double)stats->largest / area;
+  out->i = (double)stats->n_isolated_void_clusters / voids;
+  out->n = (double)stats->n_clusters / voids;
+  return PM_OK;
+}
+
 int pm_path_derivatives(int32_t n_steps, const double* x, const double* y, double* dy, double* d2y) {
   using pmh::fail;
   if (n_steps < 3) return fail(PM_EINVAL, "n_steps = %d: at least 3 samples are needed", n_steps);

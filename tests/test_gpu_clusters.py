@@ -29,6 +29,11 @@ def check(void, plastic):
     assert np.array_equal(lab.cpu().numpy().astype(np.int64), ref_lab)
     for k in KEYS:
         assert st[k] == ref[k], k
+    if st["n_void"] < void.size:
+        # Sec. 3 indicators: library (from the device counts) against the oracle
+        got, want = gc.indicators(st, void.shape[0]), oc.indicators(ref, void.shape[0])
+        for k in ("v_p", "f_p", "v_max", "i", "n"):
+            assert got[k] == pytest.approx(want[k], rel=1e-15, abs=1e-300), k
     return st
 
 

@@ -141,3 +141,44 @@ def test_path_indicators_of_linear_curves():
     ind = clusters.path_indicators(eps0, 2.0 - 0.5 * eps0, 3.0 * eps0 + 1.0)
     np.testing.assert_allclose(ind["r"], -0.5, atol=1e-12)
     np.testing.assert_allclose(ind["minus_d2sigma0"], 0.0, atol=1e-9)
+
+
+def _hand_built_grid():
+    """L = 8 periodic grid, (x2, x1) = (row, column).  Voids: A = (1, 1),
+    B = (4, 4) + (4, 5), C = (6, 1).  Plastic: (1, 2) next to A, a path
+    (2, 1) (3, 1) (4, 1) (4, 2) (4, 3) joining A to B, and a plastic-only
+    pair (2, 6) (3, 6) whose nearest void is (4, 5) (distance^2 = 2 from
+    (3, 6); A is at 10 from (2, 6), C at 18)."""
+    L = 8
+    void = np.zeros((L, L), bool)
+    plastic = np.zeros((L, L), bool)
+    for y, x in ((1, 1), (4, 4), (4, 5), (6, 1)):
+        void[y, x] = True
+    for y, x in ((1, 2), (2, 1), (3, 1), (4, 1), (4, 2), (4, 3), (2, 6), (3, 6)):
+        plastic[y, x] = True
+    return L, void, plastic
+
+
+def test_indicators_of_a_hand_built_grid():
+    """Sec. 3 indicators counted by hand: 3 void clusters (A, B, C); the
+    void-plastic phase holds A-path-B (9 pixels), C, and the plastic-only pair
+    that joins B's cluster, so 2 clusters, the largest of 11 pixels; only C
+    has no plastic neighbour.  A wrong normalisation (void pixels instead of
+    void clusters), the largest cluster taken before attachment, or f_p without
+    the 1 - f factor each fail one of these values."""
+    L, void, plastic = _hand_built_grid()
+    lab, st = clusters.analyze(void, plastic)
+    assert (st["n_void"], st["n_plastic"], st["n_void_clusters"]) == (4, 8, 3)
+    assert (st["n_clusters_raw"], st["n_isolated_void_clusters"], st["n_plastic_only_clusters"]) == (3, 1, 1)
+    assert (st["n_clusters"], st["largest"]) == (2, 11)
+    assert lab[2, 6] == lab[4, 5] == lab[1, 1] and lab[6, 1] != lab[1, 1]
+    ind = clusters.indicators(st, L)
+    assert ind["v_p"] == pytest.approx(12 / 64, abs=1e-15)
+    assert ind["f_p"] == pytest.approx((12 / 64) / (1 - 4 / 64), abs=1e-15)
+    assert ind["v_max"] == pytest.approx(11 / 64, abs=1e-15)
+    assert ind["i"] == pytest.approx(1 / 3, abs=1e-15)
+    assert ind["n"] == pytest.approx(2 / 3, abs=1e-15)
+    # an imposed f (the nominal porosity) replaces the realised one in f_p only
+    ind2 = clusters.indicators(st, L, f=0.1)
+    assert ind2["f_p"] == pytest.approx((12 / 64) / 0.9, abs=1e-15)
+    assert ind2["v_max"] == ind["v_max"]
