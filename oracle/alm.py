@@ -71,15 +71,24 @@ def norm3(a):
     return float(np.sqrt(np.sum(np.asarray(a) ** 2)))
 
 
-def divergence(sig):
-    """Backward-difference divergence of eq. 1: sum_j sigma_ij(x) - sigma_ij(x - e^j).
+FLIPS = {0: (False, False), 1: (True, True), 2: (True, False), 3: (False, True)}
+
+
+def divergence(sig, flip1=False, flip2=False):
+    """Discrete divergence of eq. 1: sum_j sigma_ij(x) - sigma_ij(x - e^j).
 
     sig: (L, L, 3, 3) indexed [x2][x1]; returns (L, L, 2) for i = 1, 2.
     Direction 1 is axis 1 (x1), direction 2 is axis 0 (x2).
+
+    flip1 / flip2: the divergence of the sign-flipped Green tensors of DG2
+    (Sec. 2).  G(-q1, q2) evaluates k_1 of eq. 2 at -q1, i.e. -conj(k_1(q1)),
+    so its strains are the differences u(x - e^1) - u(x) and the equilibrium
+    they are orthogonal to uses i conj(k_1(-q1)) = -i k_1(q1): the difference
+    sigma_i1(x) - sigma_i1(x + e^1) along that direction.
     """
     s = sig[..., :2, :2]
-    d1 = s[..., :, 0] - np.roll(s[..., :, 0], 1, axis=1)   # j = 1
-    d2 = s[..., :, 1] - np.roll(s[..., :, 1], 1, axis=0)   # j = 2
+    d1 = s[..., :, 0] - np.roll(s[..., :, 0], -1 if flip1 else 1, axis=1)   # j = 1
+    d2 = s[..., :, 1] - np.roll(s[..., :, 1], -1 if flip2 else 1, axis=0)   # j = 2
     return d1 + d2
 
 
@@ -124,6 +133,10 @@ class Solver:
         self.G = dg.green_variant_on_grid(L, p.lam0, p.mu0, p.green_variant)
         self.lam_mult = None   # Lagrange multiplier lambda (L, L, 3, 3)
         self.eps = None
+        # equilibrium of the Green tensor in use: the sign variants of DG2
+        # take the differences of their own momenta; DG1 and CG1 are judged
+        # with the backward differences of eq. 1
+        self.flips = FLIPS.get(p.green_variant, (False, False))
 
     # -- building blocks --------------------------------------------------
     def c0(self, a):
@@ -199,17 +212,17 @@ class Solver:
             prev_mean = smean
             if fixed_iters is not None:
                 if it >= fixed_iters:
-                    r_eq = float(np.sqrt(np.mean(np.sum(divergence(sig) ** 2, axis=-1)))) / ns
+                    r_eq = float(np.sqrt(np.mean(np.sum(divergence(sig, *self.flips) ** 2, axis=-1)))) / ns
                     converged = it >= 2 and r_eq < p.eta_eq and r_mac < p.eta_mac and r_cmp < p.eta_cmp
                     break
                 continue
             if it >= 2 and r_mac < p.eta_mac and r_cmp < p.eta_cmp:
-                r_eq = float(np.sqrt(np.mean(np.sum(divergence(sig) ** 2, axis=-1)))) / ns
+                r_eq = float(np.sqrt(np.mean(np.sum(divergence(sig, *self.flips) ** 2, axis=-1)))) / ns
                 if r_eq < p.eta_eq:
                     converged = True
                     break
             if it >= p.max_iter:
-                r_eq = float(np.sqrt(np.mean(np.sum(divergence(sig) ** 2, axis=-1)))) / ns
+                r_eq = float(np.sqrt(np.mean(np.sum(divergence(sig, *self.flips) ** 2, axis=-1)))) / ns
                 break
         sig = self.sigma()
         return StepResult(sig, self.eps.copy(), e, plastic, margin,

@@ -110,7 +110,9 @@ __global__ void __launch_bounds__(256) k_reduce(const Slot<T>* __restrict__ slot
 }
 
 // Backward-difference divergence of eq. 1 of the stored stress:
-// div_i(x) = sum_j sigma_ij(x) - sigma_ij(x - e^j), direction 1 = x1, and
+// div_i(x) = sum_j sigma_ij(x) - sigma_ij(x - e^j), direction 1 = x1 (with
+// x + e^j in place of x - e^j along a direction whose momentum the Green
+// tensor takes at -q_j, the sign variants of DG2), and
 // from it the equilibrium indicator eta_1, which ends the step on
 // convergence or at max_iter.  Each block stores its partial sum; the last
 // block of a slot to finish (a ticket in the slot state, taken after a
@@ -129,11 +131,15 @@ __global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, 
   using v4 = T __attribute__((ext_vector_type(4)));
   gptr<const v4> __restrict__ sg = (gptr<const v4>)glb(S.sig);
   double acc[1] = {0.0};
+  // neighbour of each direction: x - e^j, or x + e^j for a Green tensor
+  // evaluated at -q_j (its momenta make the equilibrium a difference
+  // towards x + e^j)
+  const int o1 = S.flip1 ? 1 : L - 1, o2 = S.flip2 ? 1 : L - 1;
   for (long ix = (long)lb * blockDim.x + threadIdx.x; ix < npx; ix += (long)dbps * blockDim.x) {
     const int x1 = (int)(ix & (L - 1));
     const int x2 = (int)(ix / L);
-    const long i1 = (long)x2 * L + ((x1 + L - 1) & (L - 1));   // x - e^1
-    const long i2 = (long)((x2 + L - 1) & (L - 1)) * L + x1;   // x - e^2
+    const long i1 = (long)x2 * L + ((x1 + o1) & (L - 1));   // x -/+ e^1
+    const long i2 = (long)((x2 + o2) & (L - 1)) * L + x1;   // x -/+ e^2
     const v4 a = sg[ix], b1 = sg[i1], b2 = sg[i2];
     const double d1 = ((double)a.x - (double)b1.x) + ((double)a.w - (double)b2.w);
     const double d2 = ((double)a.w - (double)b1.w) + ((double)a.y - (double)b2.y);

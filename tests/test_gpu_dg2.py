@@ -142,3 +142,21 @@ def test_dg2_invalid_arguments():
     with pytest.raises(PmError):
         pdg2.combine(bad, torch.zeros((48, 48), dtype=torch.uint8, device="cuda"),
                      [torch.zeros((4, 48, 48), device="cuda") for _ in range(4)])
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_each_variant_stops_on_its_own_equilibrium(variant):
+    """Every sign variant of DG2 converges on the equilibrium indicator of its
+    own momenta (x + e^j differences along flipped directions), in the
+    iteration the oracle stops at, with the same indicator values."""
+    L = 16
+    mask = synth.bernoulli_mask(L, 0.1, 5)
+    E = (0.2, 0.2, 0.0)
+    p = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.04, lam0=0.08, tol=1e-8, max_iter=8000,
+                        precision="fp64", green_variant=variant)
+    rg = pms.Solver(torch.tensor(mask, device="cuda"), p).step(E)
+    ro = alm.Solver(mask, alm.Params(L=L, mu0=0.04, lam0=0.08, max_iter=8000, green_variant=variant)).step(E)
+    assert rg.converged and ro.converged
+    assert rg.iters == ro.iters
+    assert rg.res_eq == pytest.approx(ro.res_eq, rel=1e-6)
+    assert rel(t33(rg.sigma), ro.sigma) <= 1e-10

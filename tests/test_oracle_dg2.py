@@ -94,3 +94,36 @@ def test_combine_is_the_plain_average():
     seq = hencky.sigma_eq(soa)
     assert np.all(seq[pl] >= 1.0 - 1e-12)          # plastic pixels sit on the yield surface
     assert np.all(seq[~pl & ~void] <= 1.0 + 1e-12)
+
+
+@pytest.mark.parametrize("mf,pairs", [(mir1, {0: 2, 2: 0, 1: 3, 3: 1}), (mir2, {0: 3, 3: 0, 1: 2, 2: 1}),
+                                      (mir12, {0: 1, 1: 0, 2: 3, 3: 2})])
+def test_each_variant_measures_its_own_equilibrium(case, mf, pairs):
+    """A variant's equilibrium indicator is that of its own momenta: under a
+    mirror it equals, iterate by iterate, the indicator of the variant it maps
+    onto (the backward differences of eq. 1 for every variant would break
+    this, since the mirror turns a backward difference into a forward one)."""
+    mask, E = case
+    for v, w in pairs.items():
+        a = run_variant(mf(mask), E, v)
+        b = run_variant(mask, E, w)
+        assert a.res_eq == pytest.approx(b.res_eq, rel=1e-10)
+        s = a.sigma
+        own = alm.divergence(s, *alm.FLIPS[v])
+        assert np.sqrt(np.mean(np.sum(own ** 2, axis=-1))) / alm.norm3(s.mean(axis=(0, 1))) == \
+            pytest.approx(a.res_eq, rel=1e-12)
+
+
+def test_every_variant_converges_on_its_own_indicator():
+    """With a reference medium soft enough to converge quickly (C0 = 0.02 x
+    matrix), all four variants reach 1e-8 on all three indicators; mirrored
+    pairs need the same number of iterations."""
+    mask = synth.bernoulli_mask(L, 0.1, 5)
+    E = (0.2, 0.2, 0.0)
+    p = alm.Params(L=L, mu0=0.04, lam0=0.08, max_iter=8000)
+    res = [alm.Solver(mask, alm.Params(**{**p.__dict__, "green_variant": v})).step(E) for v in range(4)]
+    for r in res:
+        assert r.converged and r.res_eq < 1e-8, (r.iters, r.res_eq)
+    m = mir1(mask)
+    r2 = alm.Solver(m, alm.Params(**{**p.__dict__, "green_variant": 2})).step(E)
+    assert r2.iters == res[0].iters
