@@ -282,7 +282,7 @@ struct RowLds {
   static constexpr size_t budget = lds_budget((TEAMS * TPF + 63) / 64, PM_ROW_WPE);
   static constexpr size_t stage = (size_t)TEAMS * (L / 2) * 3 * sizeof(cx<T>);
   static constexpr size_t fftb = (size_t)TEAMS * 2 * LdsSize<L>::value * sizeof(T);   // one buffer per team
-  static constexpr size_t sums = (size_t)NSUM * TEAMS * TPF * sizeof(T);
+  static constexpr size_t sums = (size_t)NSUM * TEAMS * TPF * sizeof(double);   // FP64 per-thread sums
   static constexpr bool staged = zmax(stage, zmax(fftb, sums)) <= budget;
   // FP64 row passes take two buffers wherever they fit (no spills at the
   // sizes where they do: L = 4096 at 228 VGPRs); FP32 ones only within the
@@ -645,10 +645,10 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
 
   if constexpr (POINTWISE) {
     // Pointwise step per pixel.  Per-thread partial sums
-    // (sigma 11, 22, 33, 12 and |e - eps|^2) are kept in LDS rather than
-    // registers, which keeps the kernel free of spills; block and global
-    // sums are FP64.
-    T(*lacc)[BS] = reinterpret_cast<T(*)[BS]>(smem_raw);
+    // (sigma 11, 22, 33, 12, |e - eps|^2 and the plastic count) are FP64
+    // from the first pixel on, and kept in LDS rather than registers, which
+    // keeps the kernel free of spills; block and global sums are FP64 too.
+    double(*lacc)[BS] = reinterpret_cast<double(*)[BS]>(smem_raw);
     __syncthreads();   // the region may still be read by the last FFT stage or the row build
     // ROW_INIT: the load step's E from the slot state, or from the arguments
     T E0 = (T)x.E[0], E1 = (T)x.E[1], E2 = (T)x.E[2];
@@ -657,7 +657,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       E0 = (T)st->E[0]; E1 = (T)st->E[1]; E2 = (T)st->E[2];
     }
 #pragma unroll
-    for (int i = 0; i < NSUM; ++i) lacc[i][threadIdx.x] = (T)0;
+    for (int i = 0; i < NSUM; ++i) lacc[i][threadIdx.x] = 0.0;
     const int tp = opaque(t);
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
@@ -692,9 +692,10 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
         }
         sig[ix] = v4{sg[0], sg[1], flag33(sg[2], isv), sg[3]};
         {
-          const T c0 = e[0] - en[0], c1 = e[1] - en[1], c2 = en[2], c3 = e[2] - en[3];
-          const T v6[NSUM] = {sg[0], sg[1], sg[2], sg[3], c0 * c0 + c1 * c1 + c2 * c2 + (T)2 * c3 * c3,
-                              pl ? (T)1 : (T)0};
+          const double c0 = (double)(e[0] - en[0]), c1 = (double)(e[1] - en[1]), c2 = (double)en[2],
+                       c3 = (double)(e[2] - en[3]);
+          const double v6[NSUM] = {(double)sg[0], (double)sg[1], (double)sg[2], (double)sg[3],
+                                   c0 * c0 + c1 * c1 + c2 * c2 + 2.0 * c3 * c3, pl ? 1.0 : 0.0};
 #pragma unroll
           for (int i = 0; i < NSUM; ++i) lacc[i][threadIdx.x] += v6[i];
         }
@@ -706,7 +707,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
     fence(za); fence(zb); fence(zc);
     double accd[NSUM];
 #pragma unroll
-    for (int i = 0; i < NSUM; ++i) accd[i] = (double)lacc[i][threadIdx.x];
+    for (int i = 0; i < NSUM; ++i) accd[i] = lacc[i][threadIdx.x];
     block_reduce_store<NSUM>(accd, glb(S.part) + (size_t)(blockIdx.x % BPS) * NPART);
   }
 
