@@ -115,3 +115,35 @@ def test_void_pointwise_and_zero_stress():
     assert not plastic.any()
     sig = hencky.field_stress(eps, np.ones(100, bool), 1.0, 2.0, 1.0)
     assert np.all(sig == 0.0)
+
+
+@pytest.mark.parametrize("a,expect", [(3.0, np.sqrt(3.0) - 1.0), (1.0, 1.0 / np.sqrt(3.0) - 1.0)])
+def test_margin_is_the_trial_mises_stress_minus_yield(a, expect):
+    """Hand values of the margin at a uniform R = diag(a, -a, 0) (pure
+    deviator, |dev R| = sqrt(2) a) with mu = 1, mu0 = 2, Y = 1: the trial
+    (elastic) step gives dev eps = dev R / (2 (mu + mu0)), so its stress
+    deviator is mu dev R / (mu + mu0) and its Mises stress
+    sqrt(3/2) sqrt(2) a / 3 = a / sqrt(3); the margin is that minus Y.
+    a = 3 is on the capped branch (margin sqrt(3) - 1), a = 1 elastic.  A
+    wrong sqrt(3/2), (mu + mu0) or Y would move both values."""
+    R = np.diag([a, -a, 0.0])[None]
+    eps, plastic, margin = hencky.pointwise_solve(R, np.zeros(1, bool), 1.0, 2.0, 1.0, 2.0, 4.0)
+    assert margin[0] == pytest.approx(expect, abs=1e-14)
+    assert bool(plastic[0]) == (a == 3.0)
+
+
+def test_margin_equals_mises_stress_of_the_elastic_trial_strain():
+    """Independent route: solve (C + C0):eps_t = R as if elastic, take the
+    Mises stress of C:eps_t, subtract Y; on the elastic branch that stress is
+    the returned one."""
+    rng = np.random.default_rng(12)
+    mu, lam, Y, mu0, lam0 = 1.0, 2.0, 1.0, 2.0, 4.0
+    R = _sym(rng, 400, 1.5)
+    void = np.zeros(400, bool)
+    eps, plastic, margin = hencky.pointwise_solve(R, void, mu, lam, Y, mu0, lam0)
+    eps_t = hencky.iso_inv(lam + lam0, mu + mu0, R)
+    trial = hencky.sigma_eq(hencky.iso(lam, mu, eps_t)) - Y
+    np.testing.assert_allclose(margin, trial, rtol=0, atol=1e-12)
+    el = ~plastic
+    assert el.sum() > 50 and plastic.sum() > 50
+    np.testing.assert_allclose(hencky.sigma_eq(hencky.stress(eps[el], mu, lam, Y)) - Y, margin[el], atol=1e-12)

@@ -193,3 +193,47 @@ def test_warm_start_only_changes_the_mean_strain():
     a = s1.step(E, fixed_iters=10)
     b = alm.Solver(mask, _params(L)).step(E, fixed_iters=20)
     np.testing.assert_allclose(a.sigma, b.sigma, atol=1e-13)
+
+
+def test_indicator_normalisations_on_a_hand_example():
+    """Two iterations worked by hand.  Homogeneous medium with C = C0 / 2
+    (lambda = 2, mu = 1, reference twice that), elastic throughout.  Start
+    from eps0 = E + d + delta with d uniform and delta a compatible
+    fluctuation (eps11 = a(x1 + 1) - a(x1), eps22 = b(x2 + 1) - b(x2),
+    eps12 = (c(x1 + 1) - c(x1)) / 2), lambda0 = C:eps0.  The Green step
+    turns the fluctuating tau = -C0:delta_n / 2 into +delta_n / 2
+    (G C0 G = -G on compatible fields) and imposes the mean E; the pointwise
+    step 3/2 C0:eps = C:eps_n + C0:e then gives
+      <eps_n> = E + d / 3^n,  fluctuation (2/3)^n delta,
+      e_n - eps_n = -d_{n-1} / 3 - delta_{n-1} / 6.
+    Hence after two iterations
+      eta_2 = |C:(d/3 - d/9)| / |C:(E + d/9)|,
+      r_cmp = sqrt(|d/3|^2 / 9 + <|delta|^2> (4/9) / 36) / |E|,
+    with 3-D Frobenius norms (12 and 21 both counted).  Dividing eta_2 by the
+    previous mean, dropping the factor 2 on the 12 terms or normalising r_cmp
+    by anything but |E| each changes one of these numbers."""
+    L = 8
+    rng = np.random.default_rng(21)
+    a, b, c = (0.02 * rng.normal(size=L) for _ in range(3))
+    delta = np.zeros((L, L, 3, 3))
+    delta[..., 0, 0] = (np.roll(a, -1) - a)[None, :]
+    delta[..., 1, 1] = (np.roll(b, -1) - b)[:, None]
+    delta[..., 0, 1] = delta[..., 1, 0] = (0.5 * (np.roll(c, -1) - c))[None, :]
+    E = (0.02, 0.0, 0.03)
+    Et = alm.tensor_from_voigt(E)
+    d = alm.tensor_from_voigt((0.01, 0.0, -0.02))
+    p = _params(L, max_iter=10)
+    s = alm.Solver(np.zeros((L, L), np.uint8), p)
+    s.eps = Et + d + delta
+    s.lam_mult = hencky.iso(2.0, 1.0, s.eps)
+    r = s.step(E, fixed_iters=2)
+    assert not r.plastic.any()
+    C = lambda t: hencky.iso(2.0, 1.0, t)   # noqa: E731
+    fro = lambda t: float(np.sqrt(np.sum(t * t)))   # noqa: E731
+    eta2 = fro(C(d / 3 - d / 9)) / fro(C(Et + d / 9))
+    msq = float(np.mean(np.sum(delta * delta, axis=(-2, -1))))
+    rcmp = np.sqrt(fro(d / 3) ** 2 / 9 + msq * (4.0 / 9.0) / 36.0) / fro(Et)
+    assert r.res_mac == pytest.approx(eta2, rel=1e-10)
+    assert r.res_cmp == pytest.approx(rcmp, rel=1e-10)
+    np.testing.assert_allclose(r.eps_mean, Et + d / 9, atol=1e-14)
+    np.testing.assert_allclose(r.eps - r.eps_mean, (4.0 / 9.0) * delta, atol=1e-14)
