@@ -103,8 +103,10 @@ typedef struct pm_params {
  *   sigma    device, 4 planes (11, 22, 33, 12): S(eps), exactly 0 on voids.
  *   eps      device, 4 planes: the pointwise strain of the last iteration
  *            (eps_33 -> 0 at convergence; arbitrary but finite in voids).
- *   plastic  device uint8 L*L: 1 on matrix pixels on the capped branch of the
- *            Mises law (3 mu eps_eq > Y), else 0 (Sec. 3, plastic phase).
+ *   plastic  device uint8 L*L: 1 on matrix pixels whose Mises stress equals
+ *            Y (Sec. 3, plastic phase), read from sigma within a tolerance
+ *            of 4e-6 Y (FP32) / 1e-12 Y (FP64): the capped branch of the
+ *            Mises law except for elastic pixels that close to yield.
  *   host results: <sigma>, <eps> (11, 22, 33, 12), final indicators,
  *   iterations of this step, converged flag, and the step status code.
  */

@@ -111,6 +111,11 @@ __device__ __forceinline__ T flag33(T s33, bool is_void) {
   return is_void ? -(T)0 : s33 + (T)0;
 }
 
+// 1 / x: the hardware estimate in FP32 (1 ulp; det of a positive definite
+// acoustic tensor, never 0, inf or denormal), correctly rounded in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // 1 / sqrt(x): the hardware estimate in FP32 (~1 ulp), exact in FP64.
 __device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
@@ -130,6 +135,32 @@ __device__ __forceinline__ bool hencky(const T* e, T* s, const Mat<T>& m) {
   const T pr = (T)3 * m.K * t3;
   s[0] = pr + sc * d0; s[1] = pr + sc * d1; s[2] = pr + sc * d2; s[3] = sc * d3;
   return plastic;
+}
+
+// Plastic phase of the output (Sec. 3: the matrix pixels where the Mises
+// stress equals Y), read from the stored stress: |dev sigma|^2 within a few
+// rounding units of (2/3) Y^2.  A capped stress has Mises norm Y up to
+// rounding; an elastic one has Mises norm Y plus the trial margin (negative),
+// so this agrees with the pointwise step's branch except for elastic pixels
+// within PLASTIC_TOL Y of yield.  Recovering the strain first and testing it
+// instead loses accuracy when the reference medium is soft (the strain is
+// (sigma - tau) / C0 up to the trace term).
+template <typename T>
+struct PlasticTol;
+template <>
+struct PlasticTol<float> {
+  static constexpr float value = 4e-6f;
+};
+template <>
+struct PlasticTol<double> {
+  static constexpr double value = 1e-12;
+};
+template <typename T>
+__device__ __forceinline__ bool at_yield(const T* sg, const Mat<T>& m) {
+  const T t3 = (sg[0] + sg[1] + sg[2]) * (T)(1.0 / 3.0);
+  const T d0 = sg[0] - t3, d1 = sg[1] - t3, d2 = sg[2] - t3, d3 = sg[3];
+  const T n2 = d0 * d0 + d1 * d1 + d2 * d2 + (T)2 * d3 * d3;
+  return n2 > m.sy * m.sy * ((T)1 - (T)2 * PlasticTol<T>::value);
 }
 
 // Pointwise step of one pixel: solve S(eps) + C0:eps = R with
@@ -612,8 +643,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
         T sg[4] = {q.x, q.y, q.z, q.w};
         T en[4];
         strain_from(sg, tau, isv, m, en);
-        T dummy[4];
-        const bool pl = !isv && hencky(en, dummy, m);
+        const bool pl = !isv && at_yield(sg, m);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] += (double)en[c];
         if (sig_out) {
@@ -754,7 +784,7 @@ __device__ __forceinline__ void green_apply(cx<T>* tt, cx<T> k1, cx<T> k2, const
   // b = lam0 conj(k1) k2 + mu0 k1 conj(k2) = lam0 c12 + mu0 conj(c12)
   const cx<T> b = {(lam0 + mu0) * c12.re, (lam0 - mu0) * c12.im};
   const T det = A * D - (b.re * b.re + b.im * b.im);
-  const T idet = scale / det;
+  const T idet = scale * recip(det);
   const cx<T> t11 = tt[0], t22 = tt[1], t12 = tt[2];
   const cx<T> k1c = cconj(k1), k2c = cconj(k2);
   const cx<T> w1 = cmul(k1c, t11) + cmul(k2c, t12);
