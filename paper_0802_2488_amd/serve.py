@@ -20,12 +20,14 @@ from . import solver as pms
 from . import synth
 
 
-def request_job(req, tol=1e-6, max_iter=500, precision="fp32", material=None):
-    """(device mask, params, ramp) of one request."""
+def request_job(req, tol=1e-6, max_iter=500, precision="fp32", material=None, c0=None):
+    """(device mask, params, ramp) of one request; reference medium
+    c0 x matrix (default: the soft medium of the workloads)."""
     m = dict(synth.MATERIAL if material is None else material)
+    c0 = synth.C0_SOFT if c0 is None else c0
     mask = pms.device_mask(req["L"], req["f"], req["seed"])
-    params = pms.make_params(req["L"], mu=m["mu"], lam=m["lam"], Y=m["Y"], tol=tol, max_iter=max_iter,
-                             precision=precision)
+    params = pms.make_params(req["L"], mu=m["mu"], lam=m["lam"], Y=m["Y"], mu0=c0 * m["mu"], lam0=c0 * m["lam"],
+                             tol=tol, max_iter=max_iter, precision=precision)
     path = synth.load_path(req["kind"], req["steps"], synth.default_emax(req["kind"], m["Y"], m["mu"]))
     return mask, params, path
 
@@ -37,8 +39,10 @@ def _wait_until(t0, t):
 
 
 def serve_batched(trace, pool_bytes=16 << 30, max_slots=256, tick_iters=16, tol=1e-6, max_iter=500,
-                  ignore_arrivals=False):
-    """Serve the trace through one batch; returns latencies (s), pixel-iterations, wall (s)."""
+                  ignore_arrivals=False, records=None):
+    """Serve the trace through one batch; returns latencies (s), pixel-iterations, wall (s)
+    and iterations per request.  records: a dict that receives each request's
+    step records (index -> list of batch.Record)."""
     import torch
 
     b = pmb.Batch(pool_bytes, max_slots=max_slots)
@@ -75,6 +79,8 @@ def serve_batched(trace, pool_bytes=16 << 30, max_slots=256, tick_iters=16, tol=
                 i = live.pop(s)
                 recs = b.records(s)
                 b.release(s)
+                if records is not None:
+                    records[i] = recs
                 it = sum(r.iters for r in recs)
                 iters[i] = it
                 work += trace[i]["L"] ** 2 * it
@@ -85,8 +91,9 @@ def serve_batched(trace, pool_bytes=16 << 30, max_slots=256, tick_iters=16, tol=
     return np.array(lat), work, wall, iters
 
 
-def serve_fifo(trace, tol=1e-6, max_iter=500, ignore_arrivals=False):
-    """First come, first served, one request at a time on a single solver."""
+def serve_fifo(trace, tol=1e-6, max_iter=500, ignore_arrivals=False, records=None):
+    """First come, first served, one request at a time on a single solver.
+    records: a dict that receives each request's step results."""
     import torch
 
     n = len(trace)
@@ -101,9 +108,14 @@ def serve_fifo(trace, tol=1e-6, max_iter=500, ignore_arrivals=False):
         mask, params, path = request_job(req, tol, max_iter)
         s = pms.Solver(mask, params)
         it = 0
+        res = []
         for E in path:
-            it += s.step(E, fields=False).iters
+            r = s.step(E, fields=False)
+            it += r.iters
+            res.append(r)
         s.close()
+        if records is not None:
+            records[i] = res
         iters[i] = it
         work += req["L"] ** 2 * it
         lat[i] = time.perf_counter() - t0 - (0.0 if ignore_arrivals else req["arrival"])
