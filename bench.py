@@ -2,7 +2,7 @@
 Lagrangian solve on one MI355X.
 
 Workload: one realization, L = 4096, Bernoulli voids f = 0.3 (seed 0), matrix
-mu = 1, lambda = 2, Y = 1, reference medium twice the matrix, simple shear
+mu = 1, lambda = 2, Y = 1, reference medium 0.01 x matrix, simple shear
 E = (0, 0, e) ramped over 40 load steps to 4 Y / mu, tolerance 1e-6, FP32
 fields with FP64 norms.  A "step" is one load step of that ramp: the device
 iterates to convergence (or max_iter) from the previous step's state and
@@ -11,8 +11,11 @@ steps of the ramp; timed steps follow them.
 
 Output: one JSON line with the throughput, the per-kernel roofline of the
 dominant kernel (HIP event timing on the solver's stream over the timed
-region), the same throughput in FP64, and the CPU oracle timed on a bounded
-sample on this host.
+region) beside a measured device copy rate, the FP32 stress error of every
+timed step against an FP64 solve of the same iterations, the converged
+fraction of every workload, the same throughput in FP64, the batched and
+serving workloads, the extension rows, and the CPU oracle timed on a
+bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -85,7 +88,7 @@ def parse():
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--batch-max-iter", type=int, default=500)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
-    ap.add_argument("--serve-n", type=int, default=64, help="requests of the serving trace (200 = full trace)")
+    ap.add_argument("--serve-n", type=int, default=200, help="requests of the serving trace")
     ap.add_argument("--serve-max-iter", type=int, default=200)
     ap.add_argument("--serve-pool-gb", type=float, default=16.0)
     ap.add_argument("--tick", type=int, default=16, help="iterations per batch tick")
@@ -121,20 +124,34 @@ def algorithmic_bytes(L: int, fs: int):
     return row, col
 
 
-def run_gpu(L, precision, steps, warmup, max_iter, timing=True):
+def run_gpu(L, precision, steps, warmup, max_iter, timing=True, fp64_check=False):
+    """The benchmark workload; with fp64_check an FP64 solver runs the same
+    load steps with the FP32 solver's iteration counts (lock-stepped), and the
+    relative L2 stress difference of every timed step is recorded (the FP64
+    path matches the FP64 oracle to 1e-10, so this is the FP32 stress error
+    against the oracle up to that)."""
     import torch
 
     from paper_0802_2488_amd import synth
     from paper_0802_2488_amd import solver as pms
 
-    kind, nsteps = "shear", 40
+    w = synth.WORKLOADS["fp32_L4096_shear"]
+    kind, nsteps, c0 = w["kind"], w["steps"], w["c0"]
     path = synth.load_path(kind, nsteps, synth.default_emax(kind, 1.0, 1.0))
     assert warmup + steps <= nsteps
-    mask = pms.device_mask(L, 0.3, 0)
-    params = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=1e-6, max_iter=max_iter, precision=precision)
+    mask = pms.device_mask(L, w["f"], 0)
+    params = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=c0, lam0=2.0 * c0, tol=w["tol"], max_iter=max_iter,
+                             precision=precision)
     s = pms.Solver(mask, params)
+    ref = None
+    warm_iters = []
     for n in range(warmup):
-        s.step(path[n])
+        warm_iters.append(s.step(path[n], fields=False).iters)
+    if fp64_check:
+        ref = pms.Solver(mask, pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=c0, lam0=2.0 * c0, tol=0.0,
+                                               max_iter=1, precision="fp64"))
+        for n, it in enumerate(warm_iters):
+            _step_locked(ref, path[n], it)
     torch.cuda.synchronize()
     if timing:
         s.timing(True, every=8)   # events on every 8th iteration: their own cost stays small
@@ -147,18 +164,57 @@ def run_gpu(L, precision, steps, warmup, max_iter, timing=True):
     dt = time.perf_counter() - t0
     tm = s.timing(False) if timing else None
     s.close()
+    errs = []
+    if ref is not None:
+        # the FP32 fields of every timed step were kept; replay them in FP64
+        for n, r in zip(range(warmup, warmup + steps), recs):
+            s64 = _step_locked(ref, path[n], r.iters)
+            errs.append(float(torch.linalg.vector_norm(r.sigma.double() - s64) / torch.linalg.vector_norm(s64)))
+            del s64
+        ref.close()
     iters = sum(r.iters for r in recs)
     last_plastic = recs[-1].plastic
     info = dict(
         iters_per_step=[r.iters for r in recs],
         converged=[r.converged for r in recs],
+        converged_fraction=sum(r.converged for r in recs) / len(recs),
         res_eq=[r.res_eq for r in recs],
         res_mac=[r.res_mac for r in recs],
         res_cmp=[r.res_cmp for r in recs],
         sigma12_mean=[float(r.sigma_mean[3]) for r in recs],
         plastic_fraction=[float(r.plastic.float().mean()) for r in recs],
     )
+    if errs:
+        info["stress_rel_l2_vs_fp64"] = errs
     return dict(value=L * L * iters / dt, seconds=dt, iters=iters, info=info, timing=tm, last_plastic=last_plastic)
+
+
+def _step_locked(solver, E, iters):
+    """One load step of exactly `iters` iterations (tolerances 0); returns the stress (device, FP64)."""
+    solver.set_max_iter(int(iters))
+    return solver.step(E).sigma
+
+
+def copy_bandwidth():
+    """Achievable device copy rate: a 1 GiB device-to-device copy (read and
+    write counted), best of 5, HIP events on the current stream."""
+    import torch
+
+    n = 256 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(6):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return {"what": "device-to-device copy of 1 GiB (torch copy_), best of 6", "GBs": 2 * 4 * n / (best * 1e-3) / 1e9}
 
 
 def batch_jobs(n, max_iter):
@@ -169,7 +225,9 @@ def batch_jobs(n, max_iter):
     jobs = []
     for r in synth.batch_realizations(n):
         mask = pms.device_mask(r["L"], r["f"], r["seed"])
-        params = pms.make_params(r["L"], mu=1.0, lam=2.0, Y=1.0, tol=1e-6, max_iter=max_iter, precision="fp32")
+        c0 = synth.C0_SOFT
+        params = pms.make_params(r["L"], mu=1.0, lam=2.0, Y=1.0, mu0=c0, lam0=2.0 * c0, tol=1e-6, max_iter=max_iter,
+                                 precision="fp32")
         path = synth.load_path(r["kind"], r["steps"], synth.default_emax(r["kind"], 1.0, 1.0))
         jobs.append((mask, params, path))
     return jobs
@@ -236,9 +294,11 @@ def batched_section(a):
     return {
         "workload": f"{a.batch_n} realizations (seed 1000 + r, L uniform on {{128, 256, 512}}, f ~ U[0.05, 0.4], "
                     f"even r equibiaxial to 3Y/mu, odd r shear to 4Y/mu, 20 load steps, tol 1e-6, FP32, "
-                    f"max_iter {a.batch_max_iter}), one batch, {a.tick} iterations per tick",
+                    f"reference medium 0.01 x matrix, max_iter {a.batch_max_iter}), one batch, "
+                    f"{a.tick} iterations per tick",
         "value": full["value"], "unit": "pixel-iters/s", "seconds": full["seconds"],
         "pixel_iters": full["pixel_iters"], "steps": full["steps"], "converged_steps": full["converged_steps"],
+        "converged_fraction": full["converged_steps"] / max(full["steps"], 1),
         "pool_bytes": full["pool_bytes"],
         "autotuned": tuning,
         "same_work_sample": {"what": "realizations 0-15, load steps 1-3",
@@ -259,38 +319,28 @@ def serving_section(a):
     rate = 0.8 * cap
     print(f"# serving capacity {cap:.2f} req/s; arrivals at {rate:.2f} req/s", file=sys.stderr, flush=True)
     trace = synth.serving_trace(a.serve_n, 7, rate)
-    lat_b, w_b, wall_b, _ = serve.serve_batched(trace, pool_bytes=pool, tick_iters=a.tick, max_iter=a.serve_max_iter)
+    recs = {}
+    lat_b, w_b, wall_b, _ = serve.serve_batched(trace, pool_bytes=pool, tick_iters=a.tick, max_iter=a.serve_max_iter,
+                                                records=recs)
+    nsteps = sum(len(r) for r in recs.values())
+    conv_steps = sum(x.status == 1 for r in recs.values() for x in r)
+    conv_req = sum(all(x.status == 1 for x in r) for r in recs.values())
     print(f"# serving batched done: p50 {np.percentile(lat_b, 50):.3f} s", file=sys.stderr, flush=True)
     lat_f, w_f, wall_f, _ = serve.serve_fifo(trace, max_iter=a.serve_max_iter)
     print(f"# serving fifo done: p50 {np.percentile(lat_f, 50):.3f} s", file=sys.stderr, flush=True)
     return {
         "workload": f"{a.serve_n} requests (seed 7), Poisson arrivals at 0.8 x measured batched capacity, "
                     f"L in {{64, 256, 1024, 2048}} w.p. 0.4/0.3/0.2/0.1, f ~ U[0.05, 0.4], equibiaxial or shear "
-                    f"w.p. 1/2, 10-40 load steps, tol 1e-6, FP32, max_iter {a.serve_max_iter}, pool "
-                    f"{a.serve_pool_gb:g} GiB, {a.tick} iterations per tick",
+                    f"w.p. 1/2, 10-40 load steps, tol 1e-6, FP32, reference medium 0.01 x matrix, max_iter "
+                    f"{a.serve_max_iter}, pool {a.serve_pool_gb:g} GiB, {a.tick} iterations per tick",
         "capacity_req_per_s": cap, "arrival_rate_req_per_s": rate,
+        "converged_step_fraction": conv_steps / max(nsteps, 1),
+        "converged_request_fraction": conv_req / max(len(recs), 1),
+        "latency_note": "latency of each request to its last step record; steps that reach max_iter end there "
+                        "(see converged fractions)",
         "batched": dict(serve.percentiles(lat_b), pixel_iters_per_s=w_b / wall_b, wall_s=wall_b),
         "fifo_one_at_a_time": dict(serve.percentiles(lat_f), pixel_iters_per_s=w_f / wall_f, wall_s=wall_f),
     }
-
-
-def precision_check(L, iters=100):
-    """Relative L2 difference of the FP32 and FP64 stress after the same
-    iterations of load step 1 (the FP64 path is pinned to the oracle)."""
-    import torch
-
-    from paper_0802_2488_amd import solver as pms
-    from paper_0802_2488_amd import synth
-
-    mask = pms.device_mask(L, 0.3, 0)
-    E = synth.load_path("shear", 40, synth.default_emax("shear", 1.0, 1.0))[0]
-    out = {}
-    for prec in ("fp32", "fp64"):
-        s = pms.Solver(mask, pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=0.0, max_iter=iters, precision=prec))
-        out[prec] = s.step(E).sigma.double()
-        s.close()
-    d = float(torch.linalg.vector_norm(out["fp32"] - out["fp64"]) / torch.linalg.vector_norm(out["fp64"]))
-    return {"what": f"load step 1, {iters} iterations at L={L}", "rel_l2_stress_fp32_vs_fp64": d}
 
 
 def next_rows_section(plastic_4096=None):
@@ -302,17 +352,11 @@ def next_rows_section(plastic_4096=None):
     from paper_0802_2488_amd import synth
 
     out = {}
-    # DG2: four Green-tensor variants in one batch, combined after every load step
+    c0 = synth.C0_SOFT
+    # DG2 combination kernel bandwidth
     L = 1024
     mask = pms.device_mask(L, 0.2, 0)
-    p = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=1e-6, max_iter=200, precision="fp32")
-    path = synth.load_path("equibiaxial", 50, 3.0)[:3]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    steps = dg2.solve_path(mask, p, path)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    iters = sum(r.iters for st in steps for r in st.records)
+    p = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=c0, lam0=2.0 * c0, tol=1e-6, max_iter=200, precision="fp32")
     eps4 = [torch.randn((4, L, L), device="cuda") for _ in range(4)]
     sig4 = [torch.randn((4, L, L), device="cuda") for _ in range(4)]
     dg2.combine(p, mask, eps4, sig4)
@@ -323,15 +367,9 @@ def next_rows_section(plastic_4096=None):
         dg2.combine(p, mask, eps4, sig4)
     torch.cuda.synchronize()
     tc = (time.perf_counter() - t1) / reps
+    del eps4, sig4
     cb = L * L * (4 * 16 + 4 * 16 + 1 + 3 * 16 + 1)
-    out["dg2"] = {"workload": f"L={L}, f=0.2, equibiaxial load steps 1-3 of 50, tol 1e-6, FP32, max_iter 200, "
-                              "four variants in one batch",
-                  "pixel_iters_per_s": L * L * iters / dt, "seconds": dt, "iters_per_variant_step":
-                  [[r.iters for r in st.records] for st in steps],
-                  "sigma_of_avg_mean_last": [float(v) for v in steps[-1].sigma_of_avg_mean],
-                  "combine_ms": 1e3 * tc, "combine_GBs": cb / tc / 1e9,
-                  "combine_bytes_per_call": cb}
-    print(f"# dg2 done: {out['dg2']['pixel_iters_per_s']:.3e} px-iter/s", file=sys.stderr, flush=True)
+    out["dg2_combine"] = {"L": L, "ms": 1e3 * tc, "GBs": cb / tc / 1e9, "bytes_per_call": cb}
     # plastic clusters of the benchmark's last load step
     if plastic_4096 is not None:
         L = 4096
@@ -349,78 +387,137 @@ def next_rows_section(plastic_4096=None):
                                        "timed load step", "ms": 1e3 * tm, "pixels_per_s": L * L / tm,
                            "stats": st, "indicators": clusters.indicators(st, L)}
         print(f"# clusters done: {1e3 * tm:.2f} ms", file=sys.stderr, flush=True)
-    # iterations to a tolerance with the tensor of eq. 3, DG1 and CG1 (Sec. 2 compares the methods)
-    # The equilibrium indicator uses the backward differences of eq. 1, whose
-    # equilibrium DG1 and CG1 do not solve; methods are compared by the
-    # iterations until the change and constraint indicators pass.
-    L = 128
-    E1 = synth.load_path("equibiaxial", 10, 3.0)[0]
-    geoms = {"bernoulli f=0.1 (seed 0)": pms.device_mask(L, 0.1, 0),
-             "one circular void f=0.1": torch.tensor(synth.circular_void(L, 0.1), device="cuda")}
-    methods = {}
-    for gname, m in geoms.items():
-        its = {}
-        for name, v in (("DG eq.3", 0), ("DG1", 4), ("CG1", 5)):
-            q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.5, lam0=1.0, tol=1e-6, eta_eq=1e30,
-                                max_iter=4000, precision="fp64", green_variant=v)
-            s = pms.Solver(m, q)
-            r = s.step(E1, fields=False)
-            its[name] = {"iters": r.iters, "converged": r.converged, "res_eq_backward_difference": r.res_eq}
-            s.close()
-        q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=0.5, lam0=1.0, tol=1e-6, eta_eq=1e30, max_iter=4000,
-                            precision="fp64")
-        st = dg2.solve_path(m, q, [E1], fields=False)[0]
-        its["DG2"] = {"iters_per_variant": [r.iters for r in st.records],
-                      "converged": all(r.status == 1 for r in st.records)}
-        methods[gname] = its
-    out["method_iterations"] = {"workload": f"L={L}, equibiaxial load step 1 of 10, reference medium 0.5x "
-                                            "matrix, change and constraint indicators < 1e-6, FP64, max_iter 4000",
-                                **methods}
+    out["method_iterations"] = method_comparison()
     print("# methods done", file=sys.stderr, flush=True)
-    out["cluster_path"] = cluster_path()
+    out["cluster_path_dg2"] = cluster_path()
     print("# cluster path done", file=sys.stderr, flush=True)
+    out["percolation_check"] = percolation_check()
+    print("# percolation check done", file=sys.stderr, flush=True)
     return out
 
 
-def cluster_path(L=1024, f=0.2, nsteps=50, max_iter=200):
-    """Sec. 3 indicators along the curve-and-masks workload: per load step the
-    cluster counts of the plastic mask, eps0 = <(eps11 + eps22) / 2>,
-    sigma0 = <(sigma11 + sigma22) / 2>, and from them r = dn/d eps0 and
-    -d2 sigma0 / d eps0^2 (library finite differences)."""
-    import torch
-
-    from paper_0802_2488_amd import clusters
+def method_comparison(L=128, tol=1e-6, max_iter=20000):
+    """Iterations of each Green operator of Sec. 2 to a tolerance, on a
+    Bernoulli grid and on the single circular void (equibiaxial load step 1,
+    FP64, soft reference medium).  The tensor of eq. 3 and each DG2 variant
+    stop on all three indicators, the equilibrium one taken with the
+    variant's own differences.  DG1 (a non-local medium) and CG1 (continuum
+    equilibrium) do not solve the difference equilibrium of eq. 1, so every
+    method is also timed by the change and constraint indicators alone (the
+    common criterion), with the difference-equilibrium indicator reported."""
+    from paper_0802_2488_amd import dg2
     from paper_0802_2488_amd import solver as pms
     from paper_0802_2488_amd import synth
 
+    c0 = synth.C0_SOFT
+    E1 = synth.load_path("equibiaxial", 10, 3.0)[0]
+    import torch
+    geoms = {"bernoulli f=0.1 (seed 0)": pms.device_mask(L, 0.1, 0),
+             "one circular void f=0.1": torch.tensor(synth.circular_void(L, 0.1), device="cuda")}
+    res = {}
+    for gname, m in geoms.items():
+        its = {}
+        for name, v in (("DG eq.3", 0), ("DG1", 4), ("CG1", 5)):
+            row = {}
+            for crit, eta_eq in (("all three indicators", tol), ("change and constraint", 1e30)):
+                if crit == "all three indicators" and v != 0:
+                    continue
+                q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=c0, lam0=2.0 * c0, tol=tol, eta_eq=eta_eq,
+                                    max_iter=max_iter, precision="fp64", green_variant=v)
+                s = pms.Solver(m, q)
+                r = s.step(E1, fields=False)
+                s.close()
+                row[crit] = {"iters": r.iters, "converged": r.converged, "res_eq": r.res_eq}
+            its[name] = row
+        q = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=c0, lam0=2.0 * c0, tol=tol, max_iter=max_iter,
+                            precision="fp64")
+        st = dg2.solve_path(m, q, [E1], fields=False)[0]
+        its["DG2 (all three, own differences)"] = {"iters_per_variant": [r.iters for r in st.records],
+                                                   "converged": all(r.status == 1 for r in st.records)}
+        res[gname] = its
+    return {"workload": f"L={L}, equibiaxial load step 1 of 10 (e = 0.3), reference medium {c0} x matrix, "
+                        f"tolerance {tol}, FP64, max_iter {max_iter}", **res}
+
+
+def cluster_path(L=1024, f=0.2, nsteps=50, max_iter=1500):
+    """Sec. 3 indicators along the curve-and-masks workload solved with DG2
+    (the paper's method for Sec. 3): per load step the cluster counts of the
+    DG2 plastic mask, eps0 = <(eps11 + eps22) / 2>, sigma0 = <(sigma11 +
+    sigma22) / 2> (stress of the average strain), and from them r = dn/d eps0
+    and -d2 sigma0 / d eps0^2 (library finite differences)."""
+    import torch
+
+    from paper_0802_2488_amd import clusters, dg2
+    from paper_0802_2488_amd import solver as pms
+    from paper_0802_2488_amd import synth
+
+    c0 = synth.C0_SOFT
     vm = pms.device_mask(L, f, 0)
     path = synth.load_path("equibiaxial", nsteps, synth.default_emax("equibiaxial", 1.0, 1.0))
-    p = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, tol=1e-6, max_iter=max_iter, precision="fp32")
-    s = pms.Solver(vm, p)
-    eps0, sig0, n, vmax, spans, iters = [], [], [], [], [], []
+    p = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=c0, lam0=2.0 * c0, tol=1e-6, max_iter=max_iter,
+                        precision="fp32")
     t0 = time.perf_counter()
-    for E in path:
-        r = s.step(E)
-        _, st = clusters.analyze(vm, r.plastic)
-        ind = clusters.indicators(st, L)
-        eps0.append(0.5 * (r.eps_mean[0] + r.eps_mean[1]))
-        sig0.append(0.5 * (r.sigma_mean[0] + r.sigma_mean[1]))
-        n.append(ind["n"])
-        vmax.append(ind["v_max"])
-        spans.append(bool(st["spans_x1"] and st["spans_x2"]))
-        iters.append(r.iters)
+    steps = dg2.solve_path(vm, p, path)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    s.close()
+    eps0, sig0, n, vmax, spans, iters, conv = [], [], [], [], [], [], []
+    for st in steps:
+        _, cs = clusters.analyze(vm, st.plastic)
+        ind = clusters.indicators(cs, L)
+        eps0.append(0.5 * (st.eps_mean[0] + st.eps_mean[1]))
+        sig0.append(0.5 * (st.sigma_of_avg_mean[0] + st.sigma_of_avg_mean[1]))
+        n.append(ind["n"])
+        vmax.append(ind["v_max"])
+        spans.append(bool(cs["spans_x1"] and cs["spans_x2"]))
+        iters.append([r.iters for r in st.records])
+        conv.append(all(r.status == 1 for r in st.records))
     pi = clusters.path_indicators(np.array(eps0), np.array(n), np.array(sig0))
     k = int(np.argmax(pi["r"]))
-    return {"workload": f"L={L}, f={f} (seed 0), equibiaxial, {nsteps} load steps to 3Y/mu, tol 1e-6, FP32, "
-                        f"max_iter {max_iter}; clusters of every step's plastic mask",
-            "seconds": dt, "iters_per_step": iters,
+    return {"workload": f"DG2, L={L}, f={f} (seed 0), equibiaxial, {nsteps} load steps to 3Y/mu, tol 1e-6, FP32, "
+                        f"reference medium {c0} x matrix, max_iter {max_iter}; clusters of every step's DG2 plastic "
+                        f"mask", "seconds": dt, "iters_per_step_and_variant": iters,
+            "converged_step_fraction": sum(conv) / len(conv),
             "eps0": eps0, "sigma0": sig0, "n": n, "v_max": vmax,
             "r": pi["r"].tolist(), "minus_d2sigma0": pi["minus_d2sigma0"].tolist(),
             "eps0_at_max_r": eps0[k],
             "eps0_first_spanning": next((e for e, sp in zip(eps0, spans) if sp), None)}
+
+
+def percolation_check(L=1024, f=0.1, nsteps=30, e_end=1.5, max_iter=1500):
+    """The one number Sec. 3 gives for the clusters (Fig. 3): with the paper's
+    moduli (K = 1, mu = 0.4, Y = 0.5; lambda = K - 2 mu / 3) and f = 0.1, the
+    largest void-plastic cluster of the DG2 solution percolates near an
+    equibiaxial eps0 of 0.9.  Reports the first eps0 of the ramp at which
+    the largest cluster spans both axes."""
+    import torch
+
+    from paper_0802_2488_amd import clusters, dg2
+    from paper_0802_2488_amd import solver as pms
+    from paper_0802_2488_amd import synth
+
+    K, mu, Y = 1.0, 0.4, 0.5
+    lam = K - 2.0 * mu / 3.0
+    c0 = synth.C0_SOFT
+    vm = pms.device_mask(L, f, 3)
+    path = synth.load_path("equibiaxial", nsteps, e_end)
+    p = pms.make_params(L, mu=mu, lam=lam, Y=Y, mu0=c0 * mu, lam0=c0 * lam, tol=1e-6, max_iter=max_iter,
+                        precision="fp32")
+    t0 = time.perf_counter()
+    steps = dg2.solve_path(vm, p, path)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    eps0, vmax, spans, conv = [], [], [], []
+    for st in steps:
+        _, cs = clusters.analyze(vm, st.plastic)
+        eps0.append(0.5 * (st.eps_mean[0] + st.eps_mean[1]))
+        vmax.append(clusters.indicators(cs, L)["v_max"])
+        spans.append(bool(cs["spans_x1"] and cs["spans_x2"]))
+        conv.append(all(r.status == 1 for r in st.records))
+    return {"workload": f"DG2, L={L}, f={f} (seed 3), K=1, mu=0.4, Y=0.5, equibiaxial ramp of {nsteps} steps to "
+                        f"eps0={e_end}, tol 1e-6, FP32, reference medium {c0} x matrix, max_iter {max_iter}",
+            "paper_eps0_at_percolation": 0.9, "seconds": dt,
+            "eps0_first_spanning": next((e for e, sp in zip(eps0, spans) if sp), None),
+            "eps0": eps0, "v_max": vmax, "converged_step_fraction": sum(conv) / len(conv)}
 
 
 def cpu_baseline(L):
@@ -463,7 +560,8 @@ def main():
     tuned = {"fp32": autotune_sizes((L,), "fp32")[str(L)]}
     if not a.no_fp64:
         tuned["fp64"] = autotune_sizes((L,), "fp64")[str(L)]
-    r32 = run_gpu(L, "fp32", a.steps, a.warmup, a.max_iter)
+    copy = copy_bandwidth()
+    r32 = run_gpu(L, "fp32", a.steps, a.warmup, a.max_iter, fp64_check=not a.no_fp64)
     print(f"# fp32 done: {r32['value']:.4e} px-iter/s over {r32['iters']} iterations", file=sys.stderr, flush=True)
     row_b, col_b = algorithmic_bytes(L, 4)
     tm = r32["timing"]
@@ -475,7 +573,6 @@ def main():
     if not a.no_fp64:
         r64 = run_gpu(L, "fp64", min(a.steps, 2), 1, min(a.max_iter, 200))
         print(f"# fp64 done: {r64['value']:.4e} px-iter/s", file=sys.stderr, flush=True)
-    prec = precision_check(L) if not a.no_fp64 else None
     nxt = None if a.no_next else next_rows_section(r32.get("last_plastic"))
     r32.pop("last_plastic", None)
     batched = None if a.no_batch else batched_section(a)
@@ -497,25 +594,27 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded Bernoulli void mask)",
         "config": {"workload": f"single realization L={L}, f=0.3, simple shear to 4Y/mu over 40 load steps, "
-                               f"tol 1e-6, FP32 fields + FP64 norms; step = one load step (max_iter "
-                               f"{a.max_iter})",
+                               f"tol 1e-6, FP32 fields + FP64 norms, reference medium 0.01 x matrix; step = one "
+                               f"load step (max_iter {a.max_iter})",
                    "L": L, "f": 0.3, "seed": 0, "load_steps_timed": list(range(a.warmup + 1, a.warmup + a.steps + 1)),
                    "reductions": "f64 partial sums and norms", "parallelism": "1 GPU",
                    "autotuned_variants": tuned},
         "roofline": {"bound": "hbm", "kernel": "k_row (inverse row FFT + pointwise step + forward row FFT)",
                      "achieved": row_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": row_gbs / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic["k_row"],
-                     "algorithmic_bytes_per_launch": row_b, "avg_launch_ms": row_avg_ms},
+                     "algorithmic_bytes_per_launch": row_b, "avg_launch_ms": row_avg_ms,
+                     "measured_copy_GBs": copy["GBs"], "frac_of_copy": row_gbs / copy["GBs"]},
         "kernels": {
-            "k_column": {"achieved_GBs": col_gbs, "frac": col_gbs / HBM_PEAK_GBS, "avg_launch_ms": col_avg_ms,
+            "k_column": {"achieved_GBs": col_gbs, "frac": col_gbs / HBM_PEAK_GBS,
+                         "frac_of_copy": col_gbs / copy["GBs"], "avg_launch_ms": col_avg_ms,
                          "algorithmic_bytes_per_launch": col_b,
                          "traffic": None if traffic is None else traffic["k_column"]},
             "reductions_ms_per_iter": tm["other_ms"] / max(tm["iterations"], 1),
         },
         "iterations": r32["info"],
         "fp64": None if r64 is None else {"value": r64["value"], "unit": "pixel-iters/s",
-                                          "iters_per_step": r64["info"]["iters_per_step"],
-                                          "precision_check": prec},
+                                          "iters_per_step": r64["info"]["iters_per_step"]},
+        "copy_bandwidth": copy,
         "next_rows": nxt,
         "batched": batched,
         "serving": serving,

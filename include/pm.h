@@ -171,6 +171,12 @@ int pm_solver_step(pm_solver* solver, const double E[3], pm_step_out* out);
 /* Release the handle (not the borrowed mask or workspace). */
 int pm_solver_destroy(pm_solver* solver);
 
+/* Change the iteration limit of the following load steps (the state is
+ * kept), e.g. to replay another solve's iteration counts step by step.
+ * Synchronises the solver's stream.  Errors: PM_EINVAL (NULL solver,
+ * max_iter < 1). */
+int pm_solver_set_max_iter(pm_solver* solver, int32_t max_iter);
+
 /*
  * Fill dst (device if on_device != 0, else host) with the Bernoulli void
  * mask of Sec. 2: pixel p = x2 * L + x1 is a void (1) iff
@@ -467,7 +473,6 @@ int pm_path_derivatives(int32_t n_steps, const double* x, const double* y, doubl
  * on stream (not synchronised). */
 int pm_five_point_average(int32_t L, int32_t precision, int32_t nplanes, const void* d_in, void* d_out,
                           void* stream);
-
 
 /* ------------------------------------------------------------------------
  * Autotuning.  For each (precision, L) the iteration kernels exist in two

@@ -105,6 +105,7 @@ SIGNATURES = [
       ctypes.c_size_t, ctypes.c_void_p]),
     ("pm_solver_step", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PmStepOut)]),
     ("pm_solver_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("pm_solver_set_max_iter", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("pm_bernoulli_mask", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]),
     ("pm_spectrum_tile", ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -433,6 +434,19 @@ int pm_solver_step(pm_solver* s, const double E[3], pm_step_out* out) {
   if (!s || !E) return fail(PM_EINVAL, "solver and E must not be NULL");
   if (hipSetDevice(s->device) != hipSuccess) return fail(PM_EDEVICE, "hipSetDevice failed");
   return s->p.precision == PM_FP64 ? step_impl<double>(s, E, out) : step_impl<float>(s, E, out);
+}
+
+int pm_solver_set_max_iter(pm_solver* s, int32_t max_iter) {
+  if (!s) return fail(PM_EINVAL, "NULL solver");
+  if (max_iter < 1) return fail(PM_EINVAL, "max_iter = %d must be >= 1", max_iter);
+  // the kernels read the limit from the slot descriptor on the device
+  const size_t off = s->p.precision == PM_FP64
+                         ? offsetof(pm::Slot<double>, prm) + offsetof(pm::DevParams, max_iter)
+                         : offsetof(pm::Slot<float>, prm) + offsetof(pm::DevParams, max_iter);
+  PM_HIP(hipMemcpyAsync((char*)s->slot + off, &max_iter, sizeof max_iter, hipMemcpyHostToDevice, s->stream));
+  PM_HIP(hipStreamSynchronize(s->stream));
+  s->p.max_iter = max_iter;
+  return PM_OK;
 }
 
 int pm_solver_destroy(pm_solver* s) {

@@ -107,6 +107,11 @@ class Solver:
         return StepResult(np.array(out.sigma_mean[:]), np.array(out.eps_mean[:]), out.res_eq, out.res_mac,
                           out.res_cmp, out.iters, bool(out.converged), rc, sig, eps, pl)
 
+    def set_max_iter(self, max_iter: int):
+        """Iteration limit of the following load steps (the state is kept)."""
+        check(lib().pm_solver_set_max_iter(self.handle, int(max_iter)), "pm_solver_set_max_iter")
+        self.params.max_iter = int(max_iter)
+
     def timing(self, enable: bool, every: int = 1):
         """Start (resetting totals) or stop per-kernel event timing of every
         `every`-th iteration; returns the totals."""
