@@ -403,6 +403,20 @@ int pm_dg2_combine(const pm_params* params, const uint8_t* d_void_mask, const vo
                    const void* const d_sigma[4], void* d_workspace, size_t workspace_bytes, pm_dg2_out* out,
                    void* stream);
 
+/* pm_dg2_combine without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  It allocates nothing: its partial sums
+ * live in a static device array of pm_dg2_combine_static_max_bytes() bytes
+ * (about 131 KB; one copy on every GPU the library runs on, held until the
+ * process ends), which covers every L up to PM_MAX_L.  Arguments, outputs,
+ * results and errors as pm_dg2_combine (PM_EINVAL also when an input would
+ * need more scratch than the array holds).  All calls on one GPU share the
+ * array: calls that overlap in time on one GPU (other host threads, other
+ * streams) race and must be serialised by the caller. */
+size_t pm_dg2_combine_static_max_bytes(void);
+int pm_dg2_combine_static(const pm_params* params, const uint8_t* d_void_mask, const void* const d_eps[4],
+                          const void* const d_sigma[4], pm_dg2_out* out, void* stream);
+
 
 /* ------------------------------------------------------------------------
  * Void and plastic clusters (Sec. 3).  Phases: void (mask 1), plastic
@@ -473,6 +487,7 @@ int pm_path_derivatives(int32_t n_steps, const double* x, const double* y, doubl
  * on stream (not synchronised). */
 int pm_five_point_average(int32_t L, int32_t precision, int32_t nplanes, const void* d_in, void* d_out,
                           void* stream);
+
 
 /* ------------------------------------------------------------------------
  * Autotuning.  For each (precision, L) the iteration kernels exist in two

@@ -152,6 +152,10 @@ SIGNATURES = [
     ("pm_dg2_combine", ctypes.c_int,
      [ctypes.POINTER(PmParams), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
       ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(PmDg2Out), ctypes.c_void_p]),
+    ("pm_dg2_combine_static_max_bytes", ctypes.c_size_t, []),
+    ("pm_dg2_combine_static", ctypes.c_int,
+     [ctypes.POINTER(PmParams), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+      ctypes.POINTER(PmDg2Out), ctypes.c_void_p]),
 ]
 
 _lib = None

@@ -2,6 +2,10 @@
 // strain fields of the four sign variants of the Green tensor, the
 // Hencky-Mises stress of that average, the average of the four stresses and
 // the plastic mask of the average, with fixed-order FP64 means.
+#include <mutex>
+
+#include "pm.h"
+#include "pm_host.hpp"
 #include "pm_kernels.hpp"
 
 namespace pm {
@@ -143,3 +147,90 @@ template hipError_t launch_dg2<double>(int, const DevParams&, const uint8_t*, co
                                        hipStream_t);
 
 }  // namespace pm
+
+// ---------------------------------------------------------------------------
+// The combination without a caller workspace: its partial sums live in a
+// file-scope device array of fixed size (one copy per GPU, kept until the
+// process ends), reached through the address hipGetSymbolAddress returns on
+// each device.  dg2_blocks caps the grid at 1024 blocks of 16 doubles, plus
+// the 16 means, so the array covers every L up to PM_MAX_L.
+namespace pm {
+namespace {
+
+constexpr int kScratchBlocks = 1024;
+constexpr size_t kScratchDoubles = (size_t)kScratchBlocks * 16 + 16;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of the array, looked up once per device
+// with that device current (the caller's current device).
+int scratch_on_current_device(double** out) {
+  int dev = -1;
+  PM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return pmh::fail(PM_EDEVICE, "device %d beyond the supported %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    PM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return pmh::fail(PM_EDEVICE, "no address for the DG2 scratch array on device %d", dev);
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PM_OK;
+}
+
+}  // namespace
+}  // namespace pm
+
+extern "C" {
+
+size_t pm_dg2_combine_static_max_bytes(void) { return pm::kScratchDoubles * sizeof(double); }
+
+int pm_dg2_combine_static(const pm_params* params, const uint8_t* d_void_mask, const void* const d_eps[4],
+                          const void* const d_sigma[4], pm_dg2_out* out, void* stream) {
+  using pmh::fail;
+  pm_params q;
+  int rc = pmh::check_params(params, &q);
+  if (rc != PM_OK) return rc;
+  if (!d_void_mask || !d_eps || !out) return fail(PM_EINVAL, "NULL argument");
+  for (int v = 0; v < 4; ++v) {
+    if (!d_eps[v]) return fail(PM_EINVAL, "d_eps[%d] is NULL", v);
+    if (d_sigma && !d_sigma[v]) return fail(PM_EINVAL, "d_sigma[%d] is NULL", v);
+  }
+  const int nblk = pm::dg2_blocks(q.L);
+  const size_t need = ((size_t)nblk * 16 + 16) * sizeof(double);
+  if (nblk > pm::kScratchBlocks || need > pm_dg2_combine_static_max_bytes())
+    return fail(PM_EINVAL, "L = %d needs %zu bytes of scratch, beyond the %zu of the static array", q.L, need,
+                pm_dg2_combine_static_max_bytes());
+  double* part = nullptr;
+  rc = pm::scratch_on_current_device(&part);
+  if (rc != PM_OK) return rc;
+  const pm::DevParams prm = pmh::dev_params(q);
+  hipStream_t st = (hipStream_t)stream;
+  // every block writes its own partials and the final kernel writes the
+  // means, so nothing needs clearing between calls
+  if (q.precision == PM_FP64) {
+    PM_HIP(pm::launch_dg2<double>(q.L, prm, d_void_mask, (const double* const*)d_eps,
+                                  (const double* const*)d_sigma, (double*)out->eps, (double*)out->sigma_of_avg,
+                                  (double*)out->sigma_avg, out->plastic, part, nblk, st));
+  } else {
+    PM_HIP(pm::launch_dg2<float>(q.L, prm, d_void_mask, (const float* const*)d_eps, (const float* const*)d_sigma,
+                                 (float*)out->eps, (float*)out->sigma_of_avg, (float*)out->sigma_avg, out->plastic,
+                                 part, nblk, st));
+  }
+  double means[13];
+  PM_HIP(hipMemcpyAsync(means, part + (size_t)nblk * 16, sizeof means, hipMemcpyDeviceToHost, st));
+  PM_HIP(hipStreamSynchronize(st));
+  for (int c = 0; c < 4; ++c) {
+    out->eps_mean[c] = means[c];
+    out->sigma_of_avg_mean[c] = means[4 + c];
+    out->sigma_avg_mean[c] = means[8 + c];
+  }
+  out->plastic_fraction = means[12];
+  return PM_OK;
+}
+
+}  // extern "C"
