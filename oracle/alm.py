@@ -92,6 +92,25 @@ def divergence(sig, flip1=False, flip2=False):
     return d1 + d2
 
 
+def mean_div2_continuum(sig):
+    """<|div sigma|^2> with the continuum divergence of the CG1 scheme,
+    evaluated in Fourier space as the paper does (Sec. 2, "Convergence
+    issues"): i xi_j sigma_ij(q) with xi the continuum frequencies of the
+    bins; the modes with a Nyquist component, on which the continuum Green
+    operator imposes nothing, are left out.  Parseval with the unnormalised
+    DFT: the mean over the pixels is the sum over the modes divided by L^4.
+    """
+    L = sig.shape[0]
+    S = np.fft.fft2(sig[..., :2, :2], axes=(0, 1))
+    xi = dg.frequencies(L)
+    keep = np.arange(L) != L // 2
+    x1 = xi[None, :]
+    x2 = xi[:, None]
+    v = x1[..., None] * S[..., :, 0] + x2[..., None] * S[..., :, 1]
+    w = (keep[None, :] & keep[:, None]).astype(float)
+    return float(np.sum(w[..., None] * np.abs(v) ** 2)) / L ** 4
+
+
 def divergence_fourier(sig):
     """<|div sigma|^2> evaluated in Fourier space, as the paper computes it.
 
@@ -134,8 +153,8 @@ class Solver:
         self.lam_mult = None   # Lagrange multiplier lambda (L, L, 3, 3)
         self.eps = None
         # equilibrium of the Green tensor in use: the sign variants of DG2
-        # take the differences of their own momenta; DG1 and CG1 are judged
-        # with the backward differences of eq. 1
+        # take the differences of their own momenta, CG1 the continuum
+        # divergence; DG1 (no projection) the backward differences of eq. 1
         self.flips = FLIPS.get(p.green_variant, (False, False))
 
     # -- building blocks --------------------------------------------------
@@ -171,6 +190,12 @@ class Solver:
         self.lam_mult = self.lam_mult + self.c0(e - eps_new)
         self.eps = eps_new
         return e, plastic, margin
+
+    def equilibrium_indicator(self, sig, ns):
+        """eta_1 of the scheme in use: sqrt(<|div sigma|^2>) / |<sigma>|."""
+        if self.p.green_variant == 5:
+            return float(np.sqrt(mean_div2_continuum(sig))) / ns
+        return float(np.sqrt(np.mean(np.sum(divergence(sig, *self.flips) ** 2, axis=-1)))) / ns
 
     def sigma(self):
         return hencky.field_stress(self.eps, self.void, self.p.mu, self.p.lam, self.p.Y)
@@ -212,17 +237,17 @@ class Solver:
             prev_mean = smean
             if fixed_iters is not None:
                 if it >= fixed_iters:
-                    r_eq = float(np.sqrt(np.mean(np.sum(divergence(sig, *self.flips) ** 2, axis=-1)))) / ns
+                    r_eq = self.equilibrium_indicator(sig, ns)
                     converged = it >= 2 and r_eq < p.eta_eq and r_mac < p.eta_mac and r_cmp < p.eta_cmp
                     break
                 continue
             if it >= 2 and r_mac < p.eta_mac and r_cmp < p.eta_cmp:
-                r_eq = float(np.sqrt(np.mean(np.sum(divergence(sig, *self.flips) ** 2, axis=-1)))) / ns
+                r_eq = self.equilibrium_indicator(sig, ns)
                 if r_eq < p.eta_eq:
                     converged = True
                     break
             if it >= p.max_iter:
-                r_eq = float(np.sqrt(np.mean(np.sum(divergence(sig, *self.flips) ** 2, axis=-1)))) / ns
+                r_eq = self.equilibrium_indicator(sig, ns)
                 break
         sig = self.sigma()
         return StepResult(sig, self.eps.copy(), e, plastic, margin,

@@ -100,6 +100,7 @@ Layout make_layout(const pm_params& q, bool tables, bool state) {
   lo.part2 = take((size_t)lo.ndiv * sizeof(double));
   lo.state = state ? take(sizeof(DevState)) : 0;
   lo.slot = state ? take(sizeof(pm::Slot<double>)) : 0;
+  lo.spec2 = q.green_variant == 5 ? take(L * (L / 2) * 3 * 2 * fs) : 0;
   lo.total = off;
   return lo;
 }
@@ -176,7 +177,18 @@ int iterate_once(pm_solver* s, int slot_in_chunk, int chunk_slot = 0) {
   PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, tv.row, S, 1, x, s->stream));
   if (ev) PM_HIP(hipEventRecord(ev[2], s->stream));
   PM_HIP(pm::launch_reduce<T>(S, 1, pm::row_blocks<T>(L, tv.row), s->stream));
-  PM_HIP(pm::launch_div<T>(S, 1, L, 0, s->stream));
+  if (green_kind(s->p) == pm::GK_CG1) {
+    // CG1 is judged on the continuum divergence: the stress is transformed
+    // into a second spectrum (only in iterations that evaluate the
+    // indicator; the kernels return at once otherwise)
+    pm::Extra<T> xs = pmh::extra<T>(0, pm::GATE_NEED_EQ, 1.0, nullptr);
+    xs.spec_alt = (pm::cx<T>*)(s->ws + s->lo.spec2);
+    PM_HIP(pm::launch_row<T>(L, pm::ROW_SIGFWD, 0, S, 1, xs, s->stream));
+    PM_HIP(pm::launch_col<T>(L, pm::COL_FWD, 0, S, 1, xs, s->stream));
+    PM_HIP(pm::launch_div_continuum<T>(S, 1, L, xs.spec_alt, s->stream));
+  } else {
+    PM_HIP(pm::launch_div<T>(S, 1, L, 0, s->stream));
+  }
   if (ev) PM_HIP(hipEventRecord(ev[3], s->stream));
   return PM_OK;
 }

@@ -35,6 +35,7 @@ pm::DevParams dev_params(const pm_params& q);
 // Byte offsets of one realization's buffers inside its workspace.
 struct Layout {
   size_t sig, spec, xbuf, tw, ktab, part, part2, state, slot, total;
+  size_t spec2;   // CG1 only: the stress transform for the continuum equilibrium indicator (else 0)
   int nrow;    // row-pass blocks per slot
   int ndiv;    // doubles in part2
 };

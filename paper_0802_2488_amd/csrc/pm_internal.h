@@ -12,7 +12,7 @@
 
 namespace pm {
 
-enum RowMode { ROW_ITER = 0, ROW_INIT = 1, ROW_FWD = 2, ROW_INV = 3, ROW_EMIT = 4 };
+enum RowMode { ROW_ITER = 0, ROW_INIT = 1, ROW_FWD = 2, ROW_INV = 3, ROW_EMIT = 4, ROW_SIGFWD = 5 };
 enum ColMode { COL_FWD = 1, COL_GREEN = 2, COL_INV = 4, COL_ALL = 7 };
 // Green tensor of the column pass, in bits 8.. of the column mode: the sign
 // variants of eq. 3 (slot flips), DG1 (symmetrised) or CG1 (continuum).
@@ -78,8 +78,9 @@ struct Slot {
   int32_t pad[2];
 };
 
-// Which slots of a table a launch works on.
-enum Gate { GATE_ALL = 0, GATE_RUNNING = 1, GATE_PENDING = 2 };
+// Which slots of a table a launch works on (GATE_NEED_EQ: running slots
+// whose equilibrium indicator is due this iteration).
+enum Gate { GATE_ALL = 0, GATE_RUNNING = 1, GATE_PENDING = 2, GATE_NEED_EQ = 3 };
 
 // Extra arguments of the check and output modes.
 template <typename T>
@@ -93,12 +94,14 @@ struct Extra {
   double scale;          // Green-tensor output scale (1/L^2 in the iteration)
   int32_t use_state;     // 1: E from the slot state
   int32_t gate;          // Gate: skip halted slots, or slots without a pending record
+  cx<T>* spec_alt;       // ROW_SIGFWD / column transforms: this spectrum instead of the slot's
 };
 
 template <typename T>
 __device__ __forceinline__ bool gated_out(const Extra<T>& x, const DevState* st_generic) {
   gptr<const DevState> st = glb(st_generic);
-  return (x.gate == GATE_RUNNING && st->halted) || (x.gate == GATE_PENDING && !st->pending);
+  return (x.gate == GATE_RUNNING && st->halted) || (x.gate == GATE_PENDING && !st->pending) ||
+         (x.gate == GATE_NEED_EQ && (st->halted || !st->need_eq));
 }
 
 // variant: 0 default, 1 the autotuner's alternative; it applies to ROW_ITER
@@ -127,6 +130,8 @@ template <typename T>
 hipError_t launch_reduce(const Slot<T>* slots, int nslots, int nblk, hipStream_t s);
 template <typename T>
 hipError_t launch_div(const Slot<T>* slots, int nslots, int L, int force, hipStream_t s);
+template <typename T>
+hipError_t launch_div_continuum(const Slot<T>* slots, int nslots, int L, const cx<T>* spec, hipStream_t s);
 template <typename T>
 hipError_t launch_reduce_emit(const Slot<T>* slots, int nslots, int nblk, int gate, hipStream_t s);
 template <typename T>

@@ -113,11 +113,14 @@ __device__ __forceinline__ T flag33(T s33, bool is_void) {
 
 // 1 / x: the hardware estimate in FP32 (1 ulp; det of a positive definite
 // acoustic tensor, never 0, inf or denormal), correctly rounded in FP64.
-__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+#ifndef PM_PRECISE_F32
+#define PM_PRECISE_F32 0      // 1: correctly rounded FP32 division and square root
+#endif
+__device__ __forceinline__ float recip(float x) { return PM_PRECISE_F32 ? 1.0f / x : __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // 1 / sqrt(x): the hardware estimate in FP32 (~1 ulp), exact in FP64.
-__device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
+__device__ __forceinline__ float rsq(float x) { return PM_PRECISE_F32 ? 1.0f / __fsqrt_rn(x) : rsqrtf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 
 // Hencky-Mises stress of a matrix pixel; eps = (11, 22, 33, 12).  The
@@ -504,6 +507,8 @@ __device__ __forceinline__ void stage_pair_out(gptr<cx<T>> __restrict__ g, const
 //   ROW_EMIT  inverse row FFT of the stored tau; strain recovered from the
 //             stress and tau; per-step outputs and sums of the strain
 //   ROW_FWD / ROW_INV  plain row transforms of three real planes (checks)
+//   ROW_SIGFWD forward row transform of the stored stress (11, 22, 12) into
+//             x.spec_alt (the continuum equilibrium indicator of CG1)
 template <typename T, int L, int RMAX, int TEAMS, int WT, int MODE>
 __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_ROW_WPE)))
 k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
@@ -528,7 +533,8 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   cx<T>* stg = reinterpret_cast<cx<T>*>(smem_raw) + team * (L / 2) * 3;
   const int p = xcd_remap(blockIdx.x % BPS, BPS) * TEAMS + team;
   const int ra = 2 * p, rb = 2 * p + 1;
-  gptr<cx<T>> __restrict__ gbase = glb(S.spec) + (size_t)ra * WT * 3;
+  gptr<cx<T>> __restrict__ gbase =
+      glb(MODE == ROW_SIGFWD ? x.spec_alt : S.spec) + (size_t)ra * WT * 3;
   gptr<const cx<T>> __restrict__ tw = glb(S.tw);
   gptr<const uint8_t> __restrict__ mask = glb(S.mask);
   // the stress state: (11, 22, 33, 12) of a pixel side by side, one vector
@@ -659,6 +665,17 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
     }
     block_reduce_store<4>(acc, glb(S.part2) + (size_t)(blockIdx.x % BPS) * 4);
     return;
+  }
+
+  if constexpr (MODE == ROW_SIGFWD) {
+#pragma unroll
+    for (int s = 0; s < RMAX; ++s) {
+      const int x1 = t + TPF * s;
+      const v4 a = sig[(unsigned)ra * L + x1], b = sig[(unsigned)rb * L + x1];
+      za[s] = {a.x, a.y};
+      zb[s] = {b.x, b.y};
+      zc[s] = {a.w, b.w};
+    }
   }
 
   if constexpr (MODE == ROW_FWD) {
@@ -894,7 +911,7 @@ k_column(const Slot<T>* __restrict__ slots, Extra<T> x) {
   const int w = m1 % W;                   // column within its tile
   const bool packed = (g == 0);           // block-uniform: block 0 holds column 0
   gptr<const cx<T>> __restrict__ tw = glb(S.tw);
-  gptr<cx<T>> __restrict__ tile = glb(S.spec) + (size_t)(m1 / W) * L * W * 3;
+  gptr<cx<T>> __restrict__ tile = glb(x.spec_alt ? x.spec_alt : S.spec) + (size_t)(m1 / W) * L * W * 3;
   gptr<cx<T>> __restrict__ xbuf = glb(S.xbuf);
 
   // FP32 tiles of two columns, one per lane of a pair: the pair's six
@@ -1096,6 +1113,7 @@ static hipError_t launch_row_L(int mode, int v, const Slot<T>* slots, int nslots
                : launch_row_LM<T, L, 0, ROW_ITER>(slots, nslots, x, st);
     case ROW_INIT: return launch_row_LM<T, L, 0, ROW_INIT>(slots, nslots, x, st);
     case ROW_FWD: return launch_row_LM<T, L, 0, ROW_FWD>(slots, nslots, x, st);
+    case ROW_SIGFWD: return launch_row_LM<T, L, 0, ROW_SIGFWD>(slots, nslots, x, st);
     case ROW_INV: return launch_row_LM<T, L, 0, ROW_INV>(slots, nslots, x, st);
     case ROW_EMIT: return launch_row_LM<T, L, 0, ROW_EMIT>(slots, nslots, x, st);
     default: return hipErrorInvalidValue;

@@ -109,6 +109,10 @@ __global__ void __launch_bounds__(256) k_reduce(const Slot<T>* __restrict__ slot
   }
 }
 
+template <typename T>
+__device__ __forceinline__ void finish_div(const Slot<T>& S, double (&acc)[1], int lb, int dbps, double norm,
+                                           int force);
+
 // Backward-difference divergence of eq. 1 of the stored stress:
 // div_i(x) = sum_j sigma_ij(x) - sigma_ij(x - e^j), direction 1 = x1 (with
 // x + e^j in place of x - e^j along a direction whose momentum the Green
@@ -145,6 +149,18 @@ __global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, 
     const double d2 = ((double)a.w - (double)b1.w) + ((double)a.y - (double)b2.y);
     acc[0] += d1 * d1 + d2 * d2;
   }
+  finish_div(S, acc, lb, dbps, 1.0 / S.prm.npx, force);
+}
+
+// Common end of the residual passes: every block stores its partial of
+// sum |div sigma|^2; the last block of the slot to finish (a ticket in the
+// slot state, taken after a device-scope fence that publishes the partial)
+// adds the partials in index order, forms eta_1 = sqrt(sum * norm) / |<sigma>|
+// and decides.  force: only record the indicator.
+template <typename T>
+__device__ __forceinline__ void finish_div(const Slot<T>& S, double (&acc)[1], int lb, int dbps, double norm,
+                                           int force) {
+  gptr<DevState> st = glb(S.st);
   gptr<double> part2 = glb(S.part2);
   block_reduce_store<1>(acc, part2 + lb);   // thread 0 stores the block's partial
   __shared__ int last;
@@ -167,13 +183,73 @@ __global__ void __launch_bounds__(256) k_div(const Slot<T>* __restrict__ slots, 
   if (threadIdx.x == 0) {
     st->div_ticket = 0;
     const double ns = fmax(norm4(st->sm), st->floor_s);
-    const double req = sqrt(red[0] / S.prm.npx) / ns;
+    const double req = sqrt(red[0] * norm) / ns;
     st->res_eq = req;
     if (force) return;
     if (!isfinite(red[0])) end_step(st, S, ST_NAN);
     else if (st->need_eq == 1 && req < S.prm.eta_eq) end_step(st, S, ST_CONVERGED);
     else if (st->iter >= S.prm.max_iter) end_step(st, S, ST_NOCONV);
   }
+}
+
+// The equilibrium indicator of the CG1 scheme: the continuum divergence
+// i xi_j sigma_ij(q) of the stress, evaluated on its 2-D transform (the row
+// and column forward passes have put it in `spec`, tiled and packed like
+// the iteration's spectrum), xi the continuum frequencies of the bins;
+// modes with a Nyquist component, on which the continuum Green operator
+// imposes nothing, are left out.  Over the full spectrum, bins m1 = 1 ..
+// L/2 - 1 stand for their conjugate partners too (weight 2); the packed
+// column 0 holds Z = X0 + i XN, with X0(m2) = (Z(m2) + conj Z(-m2)) / 2 the
+// transform of bin m1 = 0.  Parseval: <|div|^2> = sum / L^4.
+template <typename T>
+__global__ void __launch_bounds__(256) k_div_continuum(const Slot<T>* __restrict__ slots, int L, int WT, int dbps,
+                                                       const cx<T>* __restrict__ spec_g) {
+  const Slot<T>& S = slots[blockIdx.x / dbps];
+  const int lb = blockIdx.x % dbps;
+  gptr<DevState> st = glb(S.st);
+  if (st->halted || !st->need_eq) return;
+  gptr<const cx<T>> spec = glb(spec_g);
+  const long nq = (long)L * (L / 2);
+  const double w = 6.283185307179586476925286766559 / (double)L;
+  double acc[1] = {0.0};
+  for (long p = (long)lb * blockDim.x + threadIdx.x; p < nq; p += (long)dbps * blockDim.x) {
+    const long tile = p / ((long)L * WT);
+    const int r = (int)(p - tile * (long)L * WT);
+    const int m2 = r / WT;
+    const int m1 = (int)tile * WT + r % WT;
+    if (m2 == L / 2) continue;
+    double s[3][2];
+    if (m1 > 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<T> z = ldc(spec + p * 3 + c);
+        s[c][0] = (double)z.re;
+        s[c][1] = (double)z.im;
+      }
+    } else {
+      const int mr = (L - m2) & (L - 1);
+      const long pr = tile * (long)L * WT + (long)mr * WT;   // same tile, same column 0
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<T> z = ldc(spec + p * 3 + c), zr = ldc(spec + pr * 3 + c);
+        s[c][0] = 0.5 * ((double)z.re + (double)zr.re);
+        s[c][1] = 0.5 * ((double)z.im - (double)zr.im);
+      }
+    }
+    const double x1 = w * (double)m1;
+    const double x2 = w * (double)(m2 < L / 2 ? m2 : m2 - L);
+    const double weight = m1 > 0 ? 2.0 : 1.0;
+    double v2s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double a = x1 * s[0][k] + x2 * s[2][k];   // xi_1 sigma_11 + xi_2 sigma_12
+      const double b = x1 * s[2][k] + x2 * s[1][k];   // xi_1 sigma_12 + xi_2 sigma_22
+      v2s += a * a + b * b;
+    }
+    acc[0] += weight * v2s;
+  }
+  const double Ld = (double)L;
+  finish_div(S, acc, lb, dbps, 1.0 / (Ld * Ld * Ld * Ld), 0);
 }
 
 // <eps> from the output pass's per-block sums; with gate GATE_PENDING only
@@ -309,6 +385,13 @@ hipError_t launch_div(const Slot<T>* slots, int nslots, int L, int force, hipStr
 }
 
 template <typename T>
+hipError_t launch_div_continuum(const Slot<T>* slots, int nslots, int L, const cx<T>* spec, hipStream_t s) {
+  const int g = div_blocks(L);
+  hipLaunchKernelGGL(k_div_continuum<T>, dim3(nslots * g), dim3(256), 0, s, slots, L, tile_width<T>(L), g, spec);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_reduce_emit(const Slot<T>* slots, int nslots, int nblk, int gate, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_emit<T>, dim3(nslots), dim3(256), 0, s, slots, nblk, gate);
   return hipGetLastError();
@@ -323,6 +406,7 @@ hipError_t launch_advance(const Slot<T>* slots, int nslots, hipStream_t s) {
 #define PM_INST(T)                                                                     \
   template hipError_t launch_reduce<T>(const Slot<T>*, int, int, hipStream_t);        \
   template hipError_t launch_div<T>(const Slot<T>*, int, int, int, hipStream_t);      \
+  template hipError_t launch_div_continuum<T>(const Slot<T>*, int, int, const cx<T>*, hipStream_t); \
   template hipError_t launch_reduce_emit<T>(const Slot<T>*, int, int, int, hipStream_t); \
   template hipError_t launch_advance<T>(const Slot<T>*, int, hipStream_t);
 PM_INST(float)

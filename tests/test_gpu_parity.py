@@ -186,8 +186,34 @@ def test_iteration_locked_fp64(L, f, seed, iters):
 
 @pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 def test_iteration_locked_green_variants(variant):
+    """Every Green operator iteration-locked, with its own equilibrium
+    indicator: the variants' own differences (1-3), backward differences
+    (DG1), the continuum divergence on the stress transform (CG1)."""
     _, out = _run_locked(32, 0.2, 4, [(0.4, 0.2, 0.1)], 12, "fp64", variant=variant)
     rg, ro = out[0]
+    assert rel(to_tensor33(rg.sigma), ro.sigma) <= 1e-10
+    assert rg.res_eq == pytest.approx(ro.res_eq, rel=1e-8)
+
+
+@pytest.mark.parametrize("L,precision", [(16, "fp64"), (64, "fp64"), (256, "fp32")])
+def test_cg1_continuum_indicator_matches_oracle(L, precision):
+    """The CG1 indicator (stress forward-transformed on the device, continuum
+    divergence summed over the packed half spectrum) against the oracle's
+    full-spectrum sum, at several tile widths."""
+    _, out = _run_locked(L, 0.2, 3, [(0.3, 0.1, 0.2)], 9, precision, variant=5)
+    rg, ro = out[0]
+    assert rg.res_eq == pytest.approx(ro.res_eq, rel=1e-8 if precision == "fp64" else 1e-4)
+
+
+def test_cg1_stops_on_its_own_equilibrium():
+    L = 16
+    mask = synth.bernoulli_mask(L, 0.1, 5)
+    E = (0.2, 0.2, 0.0)
+    rg = pms.Solver(torch.tensor(mask, device="cuda"),
+                    gpu_params(L, "fp64", c0=0.02, tol=1e-8, max_iter=20000, variant=5)).step(E)
+    ro = alm.Solver(mask, oracle_params(L, c0=0.02, tol=1e-8, max_iter=20000, variant=5)).step(E)
+    assert rg.converged and ro.converged and rg.iters == ro.iters
+    assert rg.res_eq == pytest.approx(ro.res_eq, rel=1e-6)
     assert rel(to_tensor33(rg.sigma), ro.sigma) <= 1e-10
 
 

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import alm, dg
+from paper_0802_2488_amd import synth
 
 
 LAM0, MU0 = 4.0, 2.0
@@ -217,3 +218,36 @@ def test_five_point_average():
     c = np.ones((8, 8))
     c[::2, ::2] = c[1::2, 1::2] = -1.0      # a checkerboard is damped to 3/5 of its amplitude
     assert np.abs(dg.five_point_average(c) + 0.6 * c).max() < 1e-15
+
+
+def test_continuum_divergence_of_plane_waves():
+    """The CG1 equilibrium indicator (continuum divergence in Fourier space):
+    sigma_11 = A cos(2 pi k x1 / L) has d1 sigma_11 = -A (2 pi k / L) sin(.),
+    mean square A^2 (2 pi k / L)^2 / 2; sigma_12 = B cos(2 pi k x2 / L) enters
+    div_1 only (through d2), with B^2 (2 pi k / L)^2 / 2; a Nyquist
+    oscillation (-1)^x1, on which CG1 imposes nothing, counts zero."""
+    L, k, A, B = 16, 3, 0.7, -1.3
+    x = np.arange(L)
+    sig = np.zeros((L, L, 3, 3))
+    sig[..., 0, 0] = A * np.cos(2 * np.pi * k * x / L)[None, :]
+    assert alm.mean_div2_continuum(sig) == pytest.approx(A * A * (2 * np.pi * k / L) ** 2 / 2, rel=1e-12)
+    sig = np.zeros((L, L, 3, 3))
+    sig[..., 0, 1] = sig[..., 1, 0] = B * np.cos(2 * np.pi * k * x / L)[:, None]
+    assert alm.mean_div2_continuum(sig) == pytest.approx(B * B * (2 * np.pi * k / L) ** 2 / 2, rel=1e-12)
+    sig = np.zeros((L, L, 3, 3))
+    sig[..., 0, 0] = ((-1.0) ** x)[None, :]
+    sig[..., 1, 1] = 2.0
+    assert alm.mean_div2_continuum(sig) < 1e-28
+
+
+def test_cg1_converges_on_its_own_equilibrium():
+    """CG1 reaches 1e-8 on all three indicators with the continuum divergence,
+    while the backward differences of eq. 1 stay far from equilibrium."""
+    L = 16
+    mask = synth.bernoulli_mask(L, 0.1, 5)
+    p = alm.Params(L=L, mu0=0.04, lam0=0.08, max_iter=20000, green_variant=5)
+    s = alm.Solver(mask, p)
+    r = s.step((0.2, 0.2, 0.0))
+    assert r.converged and r.res_eq < 1e-8
+    back = np.sqrt(np.mean(np.sum(alm.divergence(r.sigma) ** 2, axis=-1))) / alm.norm3(r.sigma_mean)
+    assert back > 1e-3
