@@ -389,6 +389,8 @@ def next_rows_section(plastic_4096=None):
         print(f"# clusters done: {1e3 * tm:.2f} ms", file=sys.stderr, flush=True)
     out["method_iterations"] = method_comparison()
     print("# methods done", file=sys.stderr, flush=True)
+    out["fig1_strain_maps"] = fig1_strain_maps()
+    print("# fig. 1 maps done", file=sys.stderr, flush=True)
     out["cluster_path_dg2"] = cluster_path()
     print("# cluster path done", file=sys.stderr, flush=True)
     out["percolation_check"] = percolation_check()
@@ -437,6 +439,48 @@ def method_comparison(L=128, tol=1e-6, max_iter=20000):
         res[gname] = its
     return {"workload": f"L={L}, equibiaxial load step 1 of 10 (e = 0.3), reference medium {c0} x matrix, "
                         f"tolerance {tol}, FP64, max_iter {max_iter}", **res}
+
+
+def fig1_strain_maps(L=256, f=0.1, nsteps=4, e_end=0.5, c0=0.1, max_iter=3000):
+    """The comparison of Fig. 1: one centred circular void (f = 0.1), the
+    paper's moduli (K = 1, mu = 0.4, Y = 0.5), equibiaxial ramp; the strain
+    maps of CG1, CG2 (five-point average of CG1), DG1 and DG2 (average of the
+    four variants) measured by the library: checkerboard index, sharpness,
+    mean and maximum equivalent strain on the matrix pixels."""
+    import torch
+
+    from paper_0802_2488_amd import dg2, maps
+    from paper_0802_2488_amd import solver as pms
+    from paper_0802_2488_amd import synth
+
+    K, mu, Y = 1.0, 0.4, 0.5
+    lam = K - 2.0 * mu / 3.0
+    vm = torch.tensor(synth.circular_void(L, f), device="cuda")
+    path = synth.load_path("equibiaxial", nsteps, e_end)
+
+    def params(v, eta_eq=1e-6):
+        return pms.make_params(L, mu=mu, lam=lam, Y=Y, mu0=c0 * mu, lam0=c0 * lam, tol=1e-6, eta_eq=eta_eq,
+                               max_iter=max_iter, precision="fp64", green_variant=v)
+
+    res = {}
+    for name, v, eta_eq in (("CG1", 5, 1e-6), ("DG1", 4, 1e30)):
+        s = pms.Solver(vm, params(v, eta_eq))
+        recs = [s.step(E) for E in path]
+        s.close()
+        r = recs[-1]
+        res[name] = dict(maps.strain_map_metrics(r.eps, vm), iters=[x.iters for x in recs],
+                         converged=[x.converged for x in recs])
+        if name == "CG1":
+            res["CG2"] = dict(maps.strain_map_metrics(maps.five_point_average(r.eps), vm),
+                              note="five-point average of the CG1 strain")
+    steps = dg2.solve_path(vm, params(0), path)
+    res["DG2"] = dict(maps.strain_map_metrics(steps[-1].eps, vm),
+                      iters=[[x.iters for x in st.records] for st in steps],
+                      converged=[all(x.status == 1 for x in st.records) for st in steps])
+    torch.cuda.synchronize()
+    return {"workload": f"L={L}, one circular void f={f}, K=1, mu=0.4, Y=0.5, equibiaxial ramp of {nsteps} steps "
+                        f"to e={e_end}, FP64, reference medium {c0} x matrix, tolerance 1e-6 (DG1: change and "
+                        f"constraint), max_iter {max_iter}; measures of the last step's strain", **res}
 
 
 def cluster_path(L=1024, f=0.2, nsteps=50, max_iter=1500):

@@ -481,6 +481,32 @@ int pm_cluster_indicators(const pm_cluster_stats* stats, int32_t L, double void_
 int pm_path_derivatives(int32_t n_steps, const double* x, const double* y, double* dy, double* d2y);
 
 
+/* Measures of a strain map, for the comparison of the methods in Sec. 2
+ * (Fig. 1: checkerboard patterns of CG1 and CG2, blurring by DG1).  On the
+ * matrix pixels (mask 0) of an L x L strain field d_eps (device, 4 planes
+ * 11, 22, 33, 12 of the given precision), with eps_eq = [(2/3) e':e']^(1/2)
+ * and e' the 3-D deviator (Fig. 1):
+ *   mean_eq, max_eq   mean and maximum of eps_eq;
+ *   checkerboard      root mean square of the mixed second difference
+ *                     eps_eq(x) - eps_eq(x+e1) - eps_eq(x+e2) + eps_eq(x+e1+e2)
+ *                     over 2 x 2 blocks of matrix pixels, divided by mean_eq
+ *                     (0 for a field varying along one axis; 4 b / a for
+ *                     eps_eq = a + b (-1)^(x1+x2));
+ *   sharpness         root mean square of the differences between matrix
+ *                     nearest neighbours, divided by mean_eq.
+ * Periodic neighbours; FP64 sums in a fixed order.  The workspace holds the
+ * partial sums (pm_strain_map_workspace_bytes, 8-byte aligned).  Queued on
+ * stream, then synchronised.  Errors: PM_EINVAL (L, precision, NULL or
+ * small workspace). */
+typedef struct pm_strain_map_out {
+  double mean_eq, max_eq, checkerboard, sharpness;
+  int64_t matrix_pixels;
+} pm_strain_map_out;
+
+size_t pm_strain_map_workspace_bytes(int32_t L);
+int pm_strain_map_metrics(int32_t L, int32_t precision, const void* d_eps, const uint8_t* d_void_mask,
+                          void* d_workspace, size_t workspace_bytes, pm_strain_map_out* out, void* stream);
+
 /* CG2 (Sec. 2): the average of a field over each pixel and its four nearest
  * neighbours (periodic), applied plane by plane.  d_in, d_out: device,
  * nplanes x L x L values of the given precision, not overlapping.  Queued

@@ -16,6 +16,8 @@ Modules
     dg2     the DG2 average of the four sign variants of the Green tensor
             (Sec. 2, "Discrete Green functions").
     clusters  void / plastic clusters and the Sec. 3 indicators.
+    maps    measures of a strain map for the comparison of the methods
+            (Fig. 1: checkerboard index and sharpness of eps_eq).
 
 Every function states the passage it follows.  Functions without an
 independent pin say "parity unpinned" in their docstring.

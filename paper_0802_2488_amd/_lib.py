@@ -87,6 +87,11 @@ class PmClusterIndicators(ctypes.Structure):
                 ("i", ctypes.c_double), ("n", ctypes.c_double)]
 
 
+class PmStrainMapOut(ctypes.Structure):
+    _fields_ = [("mean_eq", ctypes.c_double), ("max_eq", ctypes.c_double), ("checkerboard", ctypes.c_double),
+                ("sharpness", ctypes.c_double), ("matrix_pixels", ctypes.c_int64)]
+
+
 class PmDg2Out(ctypes.Structure):
     _fields_ = [
         ("eps", ctypes.c_void_p), ("sigma_of_avg", ctypes.c_void_p), ("sigma_avg", ctypes.c_void_p),
@@ -139,6 +144,10 @@ SIGNATURES = [
      [ctypes.POINTER(PmClusterStats), ctypes.c_int32, ctypes.c_double, ctypes.POINTER(PmClusterIndicators)]),
     ("pm_path_derivatives", ctypes.c_int,
      [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("pm_strain_map_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32]),
+    ("pm_strain_map_metrics", ctypes.c_int,
+     [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+      ctypes.POINTER(PmStrainMapOut), ctypes.c_void_p]),
     ("pm_five_point_average", ctypes.c_int,
      [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("pm_autotune_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),

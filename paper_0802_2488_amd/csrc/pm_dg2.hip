@@ -2,6 +2,7 @@
 // strain fields of the four sign variants of the Green tensor, the
 // Hencky-Mises stress of that average, the average of the four stresses and
 // the plastic mask of the average, with fixed-order FP64 means.
+#include <cmath>
 #include <mutex>
 
 #include "pm.h"
@@ -148,6 +149,115 @@ template hipError_t launch_dg2<double>(int, const DevParams&, const uint8_t*, co
 
 }  // namespace pm
 
+namespace pm {
+
+// ---------------------------------------------------------------------------
+// Measures of a strain map (the comparison of the methods in Fig. 1): the
+// equivalent strain eps_eq = sqrt(2/3 e':e') (3-D deviator) on matrix pixels,
+// its mean and maximum, the checkerboard index (root mean square of the
+// mixed second difference eps_eq(x) - eps_eq(x + e1) - eps_eq(x + e2)
+// + eps_eq(x + e1 + e2) over 2 x 2 blocks of matrix pixels, over the mean)
+// and the sharpness (root mean square of the first differences between
+// matrix neighbours, over the mean).  The mixed difference vanishes for a
+// field that varies along one axis only and is 4 b for an oscillation
+// b (-1)^(x1 + x2), so it picks out the checkerboard pattern.
+constexpr int MAP_NSUM = 6;    // sum eps_eq, matrix pixels, sum d^2, blocks, sum diff^2, pairs
+
+template <typename T>
+__device__ __forceinline__ double eps_eq_at(gptr<const T> e, long npx, long p) {
+  const double a = (double)e[p], b = (double)e[npx + p], c = (double)e[2 * npx + p], d = (double)e[3 * npx + p];
+  const double t3 = (a + b + c) / 3.0;
+  const double d0 = a - t3, d1 = b - t3, d2 = c - t3;
+  return sqrt(2.0 / 3.0 * (d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * d * d));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_map_metrics(int L, const T* __restrict__ eps_g,
+                                                     const uint8_t* __restrict__ mask_g,
+                                                     double* __restrict__ partials) {
+  gptr<const T> e = glb(eps_g);
+  gptr<const uint8_t> mask = glb(mask_g);
+  const long npx = (long)L * L;
+  double acc[MAP_NSUM];
+#pragma unroll
+  for (int i = 0; i < MAP_NSUM; ++i) acc[i] = 0.0;
+  double mx = 0.0;
+  for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += (long)gridDim.x * blockDim.x) {
+    if (mask[p]) continue;
+    const int x1 = (int)(p & (L - 1)), x2 = (int)(p / L);
+    const long p1 = (long)x2 * L + ((x1 + 1) & (L - 1));               // x + e1
+    const long p2 = (long)((x2 + 1) & (L - 1)) * L + x1;               // x + e2
+    const long p12 = (long)((x2 + 1) & (L - 1)) * L + ((x1 + 1) & (L - 1));
+    const double q = eps_eq_at<T>(e, npx, p);
+    acc[0] += q;
+    acc[1] += 1.0;
+    mx = fmax(mx, q);
+    const bool m1 = !mask[p1], m2 = !mask[p2];
+    double q1 = 0.0, q2 = 0.0;
+    if (m1) {
+      q1 = eps_eq_at<T>(e, npx, p1);
+      acc[4] += (q1 - q) * (q1 - q);
+      acc[5] += 1.0;
+    }
+    if (m2) {
+      q2 = eps_eq_at<T>(e, npx, p2);
+      acc[4] += (q2 - q) * (q2 - q);
+      acc[5] += 1.0;
+    }
+    if (m1 && m2 && !mask[p12]) {
+      const double d = q - q1 - q2 + eps_eq_at<T>(e, npx, p12);
+      acc[2] += d * d;
+      acc[3] += 1.0;
+    }
+  }
+  block_reduce_store<MAP_NSUM>(acc, glb(partials) + (size_t)blockIdx.x * 8);
+  // block maximum (non-negative values): wave shuffles, then the waves in order
+  __shared__ double wmax[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) m = fmax(m, wmax[w]);
+    glb(partials)[(size_t)blockIdx.x * 8 + MAP_NSUM] = m;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_map_final(double* __restrict__ partials_g, int nblk) {
+  gptr<double> partials = glb(partials_g);
+  __shared__ double red[256][MAP_NSUM + 1];
+  double s[MAP_NSUM + 1];
+#pragma unroll
+  for (int i = 0; i <= MAP_NSUM; ++i) s[i] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+    for (int i = 0; i < MAP_NSUM; ++i) s[i] += partials[(long)b * 8 + i];
+    s[MAP_NSUM] = fmax(s[MAP_NSUM], partials[(long)b * 8 + MAP_NSUM]);
+  }
+#pragma unroll
+  for (int i = 0; i <= MAP_NSUM; ++i) red[threadIdx.x][i] = s[i];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+#pragma unroll
+      for (int i = 0; i < MAP_NSUM; ++i) red[threadIdx.x][i] += red[threadIdx.x + off][i];
+      red[threadIdx.x][MAP_NSUM] = fmax(red[threadIdx.x][MAP_NSUM], red[threadIdx.x + off][MAP_NSUM]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x <= MAP_NSUM) partials[(long)nblk * 8 + threadIdx.x] = red[0][threadIdx.x];
+}
+
+int map_blocks(int L) {
+  const long npx = (long)L * L;
+  long g = (npx + 255) / 256;
+  if (g > 1024) g = 1024;
+  return (int)g;
+}
+
+}  // namespace pm
+
 // ---------------------------------------------------------------------------
 // The combination without a caller workspace: its partial sums live in a
 // file-scope device array of fixed size (one copy per GPU, kept until the
@@ -230,6 +340,46 @@ int pm_dg2_combine_static(const pm_params* params, const uint8_t* d_void_mask, c
     out->sigma_avg_mean[c] = means[8 + c];
   }
   out->plastic_fraction = means[12];
+  return PM_OK;
+}
+
+size_t pm_strain_map_workspace_bytes(int32_t L) {
+  if (!pmh::is_pow2(L) || L < 4 || L > PM_MAX_L) return 0;
+  return ((size_t)pm::map_blocks(L) * 8 + 8) * sizeof(double);
+}
+
+int pm_strain_map_metrics(int32_t L, int32_t precision, const void* d_eps, const uint8_t* d_void_mask,
+                          void* d_workspace, size_t workspace_bytes, pm_strain_map_out* out, void* stream) {
+  using pmh::fail;
+  if (!pmh::is_pow2(L) || L < 4 || L > PM_MAX_L)
+    return fail(PM_EINVAL, "L = %d must be a power of two in [4, %d]", L, PM_MAX_L);
+  if (precision != PM_FP32 && precision != PM_FP64) return fail(PM_EINVAL, "precision must be PM_FP32 or PM_FP64");
+  if (!d_eps || !d_void_mask || !d_workspace || !out) return fail(PM_EINVAL, "NULL argument");
+  const int nblk = pm::map_blocks(L);
+  const size_t need = ((size_t)nblk * 8 + 8) * sizeof(double);
+  if (workspace_bytes < need)
+    return fail(PM_EINVAL, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, need);
+  if (((uintptr_t)d_workspace) % 8 != 0) return fail(PM_EINVAL, "workspace must be 8-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  double* part = (double*)d_workspace;
+  if (precision == PM_FP64)
+    hipLaunchKernelGGL(pm::k_map_metrics<double>, dim3(nblk), dim3(256), 0, st, L, (const double*)d_eps,
+                       d_void_mask, part);
+  else
+    hipLaunchKernelGGL(pm::k_map_metrics<float>, dim3(nblk), dim3(256), 0, st, L, (const float*)d_eps,
+                       d_void_mask, part);
+  PM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(pm::k_map_final, dim3(1), dim3(256), 0, st, part, nblk);
+  PM_HIP(hipGetLastError());
+  double r[8];
+  PM_HIP(hipMemcpyAsync(r, part + (size_t)nblk * 8, sizeof(double) * (pm::MAP_NSUM + 1), hipMemcpyDeviceToHost, st));
+  PM_HIP(hipStreamSynchronize(st));
+  out->matrix_pixels = (int64_t)r[1];
+  out->mean_eq = r[1] > 0 ? r[0] / r[1] : 0.0;
+  out->max_eq = r[pm::MAP_NSUM];
+  const double m = out->mean_eq > 0 ? out->mean_eq : 1.0;
+  out->checkerboard = r[3] > 0 ? std::sqrt(r[2] / r[3]) / m : 0.0;
+  out->sharpness = r[5] > 0 ? std::sqrt(r[4] / r[5]) / m : 0.0;
   return PM_OK;
 }
 

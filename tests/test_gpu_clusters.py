@@ -94,3 +94,49 @@ def test_path_derivatives_library_matches_oracle():
         np.testing.assert_allclose(d2l, d2o, rtol=0, atol=1e-8 * (np.abs(d2o).max() + 1.0))
     with pytest.raises(Exception):
         gc.path_derivatives(np.array([0.0, 1.0, 1.0]), np.zeros(3))
+
+
+def _map_metrics_gpu(eps_planes, void, precision):
+    import ctypes
+
+    from paper_0802_2488_amd import _lib
+    L = void.shape[0]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    e = torch.tensor(eps_planes, dtype=dt, device="cuda").contiguous()
+    m = torch.tensor(void.astype(np.uint8), device="cuda")
+    n = _lib.lib().pm_strain_map_workspace_bytes(L)
+    ws = torch.empty(n // 8 + 1, dtype=torch.float64, device="cuda")
+    out = _lib.PmStrainMapOut()
+    prec = _lib.PM_FP64 if precision == "fp64" else _lib.PM_FP32
+    _lib.check(_lib.lib().pm_strain_map_metrics(L, prec, e.data_ptr(), m.data_ptr(), ws.data_ptr(), n,
+                                                ctypes.byref(out), torch.cuda.current_stream().cuda_stream),
+               "pm_strain_map_metrics")
+    return {k: getattr(out, k) for k, _ in out._fields_}, e
+
+
+@pytest.mark.parametrize("L,f,precision", [(8, 0.2, "fp64"), (64, 0.1, "fp64"), (256, 0.3, "fp32")])
+def test_strain_map_metrics_match_oracle(L, f, precision):
+    """Fig. 1 measures (mean / max eps_eq, checkerboard index, sharpness) of
+    the library against the oracle, on a random field and on a solved one."""
+    from oracle import maps
+    void = synth.bernoulli_mask(L, f, 4).astype(bool)
+    rng = np.random.default_rng(L)
+    planes = rng.normal(size=(4, L, L)) * 0.2
+    got, e = _map_metrics_gpu(planes, void, precision)
+    want = maps.strain_map_metrics(alm_from_planes(e.cpu().double().numpy()), void)
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    for k in ("mean_eq", "max_eq", "checkerboard", "sharpness"):
+        assert got[k] == pytest.approx(want[k], rel=tol), k
+    assert got["matrix_pixels"] == want["matrix_pixels"]
+    s = pms.Solver(torch.tensor(void.astype(np.uint8), device="cuda"),
+                   pms.make_params(L, tol=0.0, max_iter=20, precision=precision))
+    r = s.step((0.3, 0.3, 0.0))
+    got, e = _map_metrics_gpu(r.eps.cpu().numpy(), void, precision)
+    want = maps.strain_map_metrics(alm_from_planes(r.eps.cpu().double().numpy()), void)
+    for k in ("mean_eq", "max_eq", "checkerboard", "sharpness"):
+        assert got[k] == pytest.approx(want[k], rel=tol), k
+
+
+def alm_from_planes(p):
+    from oracle import alm
+    return alm.from_voigt4(np.moveaxis(p, 0, -1))
