@@ -24,6 +24,11 @@ namespace {
 constexpr int NLOG = 12;                  // L = 4 .. 8192
 constexpr int NGROUP = 2 * NLOG;          // (precision, log2 L)
 constexpr size_t SLOT_DESC = sizeof(pm::Slot<double>);
+// Streams the (precision, L) groups of a tick run on: groups do not depend on
+// one another, so one group's column pass (arithmetic bound) can run beside
+// another's row pass (memory bound).  Three keep one of the process's four
+// hardware queues for the engine's own stream.
+constexpr int NGS = 3;
 
 int log2i(int L) {
   int k = 0;
@@ -146,6 +151,8 @@ struct pm_batch {
   int max_slots;
   hipStream_t user;          // the caller's stream
   hipStream_t stream;        // the engine's own stream (default priority), capturable
+  hipStream_t gstream[NGS];  // group streams (default priority), forked from and joined to `stream`
+  hipEvent_t fork_ev, join_ev[NGS];
   hipEvent_t ev_user;        // orders the engine's work after the caller's
   int device;
   Fixed fx;
@@ -231,27 +238,27 @@ int rebuild_table(pm_batch* b) {
 }
 
 template <typename T>
-int iterate_group(pm_batch* b, int g) {
+int iterate_group(pm_batch* b, int g, hipStream_t st) {
   const int L = group_L(g), n = b->grp_count[g];
   const pm::Slot<T>* tab = dev_table<T>(b, g);
   const pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_RUNNING, 1.0 / ((double)L * (double)L), nullptr);
   const pm::Tuning tv = pm::get_tuning(group_fp64(g) ? PM_FP64 : PM_FP32, L);
-  PM_HIP(pm::launch_col<T>(L, pm::COL_ALL, tv.col, tab, n, x, b->stream));
-  PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, tv.row, tab, n, x, b->stream));
-  PM_HIP(pm::launch_reduce<T>(tab, n, pm::row_blocks<T>(L, tv.row), b->stream));
-  PM_HIP(pm::launch_div<T>(tab, n, L, 0, b->stream));
+  PM_HIP(pm::launch_col<T>(L, pm::COL_ALL, tv.col, tab, n, x, st));
+  PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, tv.row, tab, n, x, st));
+  PM_HIP(pm::launch_reduce<T>(tab, n, pm::row_blocks<T>(L, tv.row), st));
+  PM_HIP(pm::launch_div<T>(tab, n, L, 0, st));
   return PM_OK;
 }
 
 // Output pass and record for slots whose step ended, then the next step.
 template <typename T>
-int finish_group(pm_batch* b, int g) {
+int finish_group(pm_batch* b, int g, hipStream_t st) {
   const int L = group_L(g), n = b->grp_count[g];
   const pm::Slot<T>* tab = dev_table<T>(b, g);
   const pm::Extra<T> x = pmh::extra<T>(0, pm::GATE_PENDING, 1.0, nullptr);
-  PM_HIP(pm::launch_row<T>(L, pm::ROW_EMIT, 0, tab, n, x, b->stream));
-  PM_HIP(pm::launch_reduce_emit<T>(tab, n, pm::row_blocks<T>(L, 0), pm::GATE_PENDING, b->stream));
-  PM_HIP(pm::launch_advance<T>(tab, n, b->stream));
+  PM_HIP(pm::launch_row<T>(L, pm::ROW_EMIT, 0, tab, n, x, st));
+  PM_HIP(pm::launch_reduce_emit<T>(tab, n, pm::row_blocks<T>(L, 0), pm::GATE_PENDING, st));
+  PM_HIP(pm::launch_advance<T>(tab, n, st));
   return PM_OK;
 }
 
@@ -263,19 +270,30 @@ int sync_in(pm_batch* b) {
 }
 
 // All launches of one tick: iters iterations of every group, then the end of
-// the load steps that finished.
+// the load steps that finished.  Each group runs on a group stream forked
+// from the engine's stream (groups share no data, and every slot's work
+// stays in order on its group's stream); the engine's stream joins them
+// all at the end, so the tick is one unit for the caller and for a graph.
 int tick_launches(pm_batch* b, int iters) {
-  for (int it = 0; it < iters; ++it) {
-    for (int g = 0; g < NGROUP; ++g) {
-      if (!b->grp_count[g]) continue;
-      int rc = group_fp64(g) ? iterate_group<double>(b, g) : iterate_group<float>(b, g);
+  int active[NGROUP], na = 0;
+  for (int g = 0; g < NGROUP; ++g)
+    if (b->grp_count[g]) active[na++] = g;
+  const int ns = std::min(na, NGS);
+  if (ns > 0) PM_HIP(hipEventRecord(b->fork_ev, b->stream));
+  for (int k = 0; k < ns; ++k) PM_HIP(hipStreamWaitEvent(b->gstream[k], b->fork_ev, 0));
+  for (int a = 0; a < na; ++a) {
+    const int g = active[a];
+    hipStream_t st = b->gstream[a % NGS];
+    for (int it = 0; it < iters; ++it) {
+      int rc = group_fp64(g) ? iterate_group<double>(b, g, st) : iterate_group<float>(b, g, st);
       if (rc != PM_OK) return rc;
     }
-  }
-  for (int g = 0; g < NGROUP; ++g) {
-    if (!b->grp_count[g]) continue;
-    int rc = group_fp64(g) ? finish_group<double>(b, g) : finish_group<float>(b, g);
+    int rc = group_fp64(g) ? finish_group<double>(b, g, st) : finish_group<float>(b, g, st);
     if (rc != PM_OK) return rc;
+  }
+  for (int k = 0; k < ns; ++k) {
+    PM_HIP(hipEventRecord(b->join_ev[k], b->gstream[k]));
+    PM_HIP(hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
   }
   return PM_OK;
 }
@@ -424,6 +442,11 @@ int pm_batch_create(pm_batch** out, void* d_pool, size_t pool_bytes, int32_t max
     if (b->hstates) (void)hipHostFree(b->hstates);
     if (b->stage_done) (void)hipEventDestroy(b->stage_done);
     if (b->ev_user) (void)hipEventDestroy(b->ev_user);
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    for (int k = 0; k < NGS; ++k) {
+      if (b->join_ev[k]) (void)hipEventDestroy(b->join_ev[k]);
+      if (b->gstream[k]) (void)hipStreamDestroy(b->gstream[k]);
+    }
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return code;
@@ -431,8 +454,15 @@ int pm_batch_create(pm_batch** out, void* d_pool, size_t pool_bytes, int32_t max
   if (hipGetDevice(&b->device) != hipSuccess) return cleanup(fail(PM_EDEVICE, "hipGetDevice failed"));
   if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
     return cleanup(fail(PM_EDEVICE, "hipStreamCreate failed"));
-  if (hipEventCreateWithFlags(&b->ev_user, hipEventDisableTiming) != hipSuccess)
+  if (hipEventCreateWithFlags(&b->ev_user, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(PM_EDEVICE, "hipEventCreate failed"));
+  for (int k = 0; k < NGS; ++k) {
+    if (hipStreamCreateWithFlags(&b->gstream[k], hipStreamNonBlocking) != hipSuccess)
+      return cleanup(fail(PM_EDEVICE, "hipStreamCreate failed"));
+    if (hipEventCreateWithFlags(&b->join_ev[k], hipEventDisableTiming) != hipSuccess)
+      return cleanup(fail(PM_EDEVICE, "hipEventCreate failed"));
+  }
   if (hipHostMalloc((void**)&b->stage, (size_t)max_slots * SLOT_DESC, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&b->hstates, (size_t)max_slots * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(PM_EDEVICE, "pinned host allocation failed"));
@@ -639,6 +669,14 @@ int pm_batch_destroy(pm_batch* b) {
   (void)hipStreamSynchronize(b->stream);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->ev_user) (void)hipEventDestroy(b->ev_user);
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  for (int k = 0; k < NGS; ++k) {
+    if (b->gstream[k]) {
+      (void)hipStreamSynchronize(b->gstream[k]);
+      (void)hipStreamDestroy(b->gstream[k]);
+    }
+    if (b->join_ev[k]) (void)hipEventDestroy(b->join_ev[k]);
+  }
   if (b->stream) (void)hipStreamDestroy(b->stream);
   if (b->stage) (void)hipHostFree(b->stage);
   if (b->hstates) (void)hipHostFree(b->hstates);
