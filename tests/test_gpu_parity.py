@@ -505,3 +505,24 @@ def test_kernel_timing_all_or_every_nth_iteration():
     chunk = 128   # the default chunk at L = 256 holds all 40 iterations
     assert t2["iterations"] == len(range(0, min(40, chunk), 4))
     assert 0.5 < (t2["row_ms"] / t2["row_launches"]) / (t1["row_ms"] / t1["row_launches"]) < 2.0
+
+
+def test_fp32_converged_against_converged_oracle():
+    """FP32 solves run to their own tolerance (1e-6) against oracle solves
+    converged to 1e-10, over the first two load steps of the FP64 parity
+    grid with a reference medium that converges (0.02 x matrix): stress
+    within 1e-4, plastic mask exact outside the 1e-5 Y band."""
+    w = synth.WORKLOADS["fp64_L64"]
+    L, c0 = w["L"], 0.02
+    mask = synth.bernoulli_mask(L, w["f"], 0)
+    path = synth.load_path(w["kind"], w["steps"], 3.0)[:2]
+    g = pms.Solver(torch.tensor(mask, device="cuda"), gpu_params(L, "fp32", c0=c0, tol=1e-6, max_iter=20000))
+    o = alm.Solver(mask, oracle_params(L, c0=c0, tol=1e-10, max_iter=40000))
+    for E in path:
+        rg = g.step(E)
+        ro = o.step(E)
+        assert rg.converged and ro.converged
+        assert rel(to_tensor33(rg.sigma), ro.sigma) <= 1e-4
+        band = np.abs(ro.margin) <= 1e-5
+        assert np.array_equal(rg.plastic.cpu().numpy().astype(bool)[~band], ro.plastic[~band])
+    g.close()
