@@ -537,7 +537,13 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       glb(MODE == ROW_SIGFWD ? x.spec_alt : S.spec) + (size_t)ra * WT * 3;
   gptr<const cx<T>> __restrict__ tw = glb(S.tw);
   gptr<const uint8_t> __restrict__ mask = glb(S.mask);
-  // the stress state: (11, 22, 33, 12) of a pixel side by side, one vector
+  // the stress state: (11, 22, 33, 12) of a pixel side by side, one vector.
+  // The iteration streams it in and out once per pass, and it is larger than
+  // the caches (268 MB at L = 4096 FP32), so those loads and stores carry the
+  // non-temporal hint (measured: the row pass 8 % faster at L = 4096, 4 % at
+  // 8192).  The spectrum keeps the default policy: adjacent row pairs share
+  // its cache lines, and the column pass reads it back from the Infinity
+  // Cache where it fits.
   using v4 = T __attribute__((ext_vector_type(4)));
   gptr<v4> __restrict__ sig = (gptr<v4>)glb(S.sig);
   const Mat<T> m = make_mat<T>(S.prm);
@@ -558,7 +564,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       const unsigned ix = (unsigned)(half ? rb : ra) * L + tt + TPF * s;
       if constexpr (MODE != ROW_ITER) mk[s][half] = mask[ix];
       if constexpr (MODE == ROW_ITER) {
-        const v4 q = sig[ix];
+        const v4 q = __builtin_nontemporal_load(sig + ix);
         so[s][half][0] = q.x; so[s][half][1] = q.y; so[s][half][2] = q.z; so[s][half][3] = q.w;
       }
     }
@@ -737,7 +743,7 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
           else { e[0] = zb[s].re; e[1] = zb[s].im; e[2] = zc[s].im; }
           pl = alm_point(e, so[s][half], isv, m, en, sg, tau);
         }
-        sig[ix] = v4{sg[0], sg[1], flag33(sg[2], isv), sg[3]};
+        __builtin_nontemporal_store(v4{sg[0], sg[1], flag33(sg[2], isv), sg[3]}, sig + ix);
         {
           const double c0 = (double)(e[0] - en[0]), c1 = (double)(e[1] - en[1]), c2 = (double)en[2],
                        c3 = (double)(e[2] - en[3]);
