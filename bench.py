@@ -392,6 +392,10 @@ def next_rows_section(plastic_4096=None):
     out["fig1_strain_maps"] = fig1_strain_maps()
     print("# fig. 1 maps done", file=sys.stderr, flush=True)
     out["cluster_path_dg2"] = cluster_path()
+    # the same curve run to the tolerance: FP64 (the FP32 primal residual
+    # has a floor above 1e-6 at small loads), on a grid whose 50 steps all
+    # converge within the iteration limit
+    out["cluster_path_dg2_converged"] = cluster_path(L=256, max_iter=20000, precision="fp64", tick_iters=64)
     print("# cluster path done", file=sys.stderr, flush=True)
     out["percolation_check"] = percolation_check()
     print("# percolation check done", file=sys.stderr, flush=True)
@@ -483,7 +487,7 @@ def fig1_strain_maps(L=256, f=0.1, nsteps=4, e_end=0.5, c0=0.1, max_iter=3000):
                         f"constraint), max_iter {max_iter}; measures of the last step's strain", **res}
 
 
-def cluster_path(L=1024, f=0.2, nsteps=50, max_iter=1500):
+def cluster_path(L=1024, f=0.2, nsteps=50, max_iter=1500, precision="fp32", tick_iters=16):
     """Sec. 3 indicators along the curve-and-masks workload solved with DG2
     (the paper's method for Sec. 3): per load step the cluster counts of the
     DG2 plastic mask, eps0 = <(eps11 + eps22) / 2>, sigma0 = <(sigma11 +
@@ -499,9 +503,9 @@ def cluster_path(L=1024, f=0.2, nsteps=50, max_iter=1500):
     vm = pms.device_mask(L, f, 0)
     path = synth.load_path("equibiaxial", nsteps, synth.default_emax("equibiaxial", 1.0, 1.0))
     p = pms.make_params(L, mu=1.0, lam=2.0, Y=1.0, mu0=c0, lam0=2.0 * c0, tol=1e-6, max_iter=max_iter,
-                        precision="fp32")
+                        precision=precision)
     t0 = time.perf_counter()
-    steps = dg2.solve_path(vm, p, path)
+    steps = dg2.solve_path(vm, p, path, tick_iters=tick_iters)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     eps0, sig0, n, vmax, spans, iters, conv = [], [], [], [], [], [], []
@@ -517,7 +521,8 @@ def cluster_path(L=1024, f=0.2, nsteps=50, max_iter=1500):
         conv.append(all(r.status == 1 for r in st.records))
     pi = clusters.path_indicators(np.array(eps0), np.array(n), np.array(sig0))
     k = int(np.argmax(pi["r"]))
-    return {"workload": f"DG2, L={L}, f={f} (seed 0), equibiaxial, {nsteps} load steps to 3Y/mu, tol 1e-6, FP32, "
+    return {"workload": f"DG2, L={L}, f={f} (seed 0), equibiaxial, {nsteps} load steps to 3Y/mu, tol 1e-6, "
+                        f"{precision.upper()}, "
                         f"reference medium {c0} x matrix, max_iter {max_iter}; clusters of every step's DG2 plastic "
                         f"mask", "seconds": dt, "iters_per_step_and_variant": iters,
             "converged_step_fraction": sum(conv) / len(conv),
@@ -527,7 +532,7 @@ def cluster_path(L=1024, f=0.2, nsteps=50, max_iter=1500):
             "eps0_first_spanning": next((e for e, sp in zip(eps0, spans) if sp), None)}
 
 
-def percolation_check(L=1024, f=0.1, nsteps=30, e_end=1.5, max_iter=1500):
+def percolation_check(L=1024, f=0.1, nsteps=30, e_end=1.5, max_iter=20000, precision="fp64", tick_iters=64):
     """The one number Sec. 3 gives for the clusters (Fig. 3): with the paper's
     moduli (K = 1, mu = 0.4, Y = 0.5; lambda = K - 2 mu / 3) and f = 0.1, the
     largest void-plastic cluster of the DG2 solution percolates near an
@@ -545,23 +550,26 @@ def percolation_check(L=1024, f=0.1, nsteps=30, e_end=1.5, max_iter=1500):
     vm = pms.device_mask(L, f, 3)
     path = synth.load_path("equibiaxial", nsteps, e_end)
     p = pms.make_params(L, mu=mu, lam=lam, Y=Y, mu0=c0 * mu, lam0=c0 * lam, tol=1e-6, max_iter=max_iter,
-                        precision="fp32")
+                        precision=precision)
     t0 = time.perf_counter()
-    steps = dg2.solve_path(vm, p, path)
+    steps = dg2.solve_path(vm, p, path, tick_iters=tick_iters)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    eps0, vmax, spans, conv = [], [], [], []
+    eps0, vmax, spans, conv, iters = [], [], [], [], []
     for st in steps:
         _, cs = clusters.analyze(vm, st.plastic)
         eps0.append(0.5 * (st.eps_mean[0] + st.eps_mean[1]))
         vmax.append(clusters.indicators(cs, L)["v_max"])
         spans.append(bool(cs["spans_x1"] and cs["spans_x2"]))
         conv.append(all(r.status == 1 for r in st.records))
+        iters.append(max(r.iters for r in st.records))
     return {"workload": f"DG2, L={L}, f={f} (seed 3), K=1, mu=0.4, Y=0.5, equibiaxial ramp of {nsteps} steps to "
-                        f"eps0={e_end}, tol 1e-6, FP32, reference medium {c0} x matrix, max_iter {max_iter}",
+                        f"eps0={e_end}, tol 1e-6, {precision.upper()}, reference medium {c0} x matrix, "
+                        f"max_iter {max_iter}",
             "paper_eps0_at_percolation": 0.9, "seconds": dt,
             "eps0_first_spanning": next((e for e, sp in zip(eps0, spans) if sp), None),
-            "eps0": eps0, "v_max": vmax, "converged_step_fraction": sum(conv) / len(conv)}
+            "eps0": eps0, "v_max": vmax, "max_iters_per_step": iters,
+            "converged_step_fraction": sum(conv) / len(conv)}
 
 
 def cpu_baseline(L):
