@@ -165,7 +165,8 @@ int green_kind(const pm_params& q) {
 template <typename T>
 int iterate_once(pm_solver* s, int slot_in_chunk, int chunk_slot = 0) {
   const int L = s->p.L;
-  const pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_RUNNING, 1.0 / ((double)L * (double)L), nullptr);
+  pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_RUNNING, 1.0 / ((double)L * (double)L), nullptr);
+  x.stream_state = pmh::stream_state((size_t)L * L * 4 * sizeof(T));
   const pm::Slot<T>* S = dslot<T>(s);
   hipEvent_t* ev = s->timing && slot_in_chunk % s->timing_every == 0
                       ? &s->tev[4 * ((size_t)chunk_slot * s->chunk + slot_in_chunk)]

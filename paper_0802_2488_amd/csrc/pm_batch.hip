@@ -162,6 +162,7 @@ struct pm_batch {
   // device table: running slots grouped by (precision, L)
   bool dirty;
   int grp_begin[NGROUP], grp_count[NGROUP];
+  size_t table_state_bytes;  // stress states of the slots in the table (all groups)
   unsigned char* stage;      // pinned copy of the table being uploaded
   DevState* hstates;         // pinned readback of the slot states
   hipEvent_t stage_done;
@@ -217,6 +218,7 @@ int rebuild_table(pm_batch* b) {
   if (!b->dirty) return PM_OK;
   PM_HIP(hipEventSynchronize(b->stage_done));   // the previous upload has left the stage
   int n = 0;
+  size_t state_bytes = 0;
   for (int i = 0; i < b->max_slots; ++i) b->slots[i].in_table = false;
   for (int g = 0; g < NGROUP; ++g) {
     b->grp_begin[g] = n;
@@ -225,10 +227,12 @@ int rebuild_table(pm_batch* b) {
       if (!h.used || h.finished || h.group != g) continue;
       h.in_table = true;
       memcpy(b->stage + (size_t)n * SLOT_DESC, h.desc, SLOT_DESC);
+      state_bytes += (size_t)h.q.L * h.q.L * 4 * (h.q.precision == PM_FP64 ? 8 : 4);
       ++n;
     }
     b->grp_count[g] = n - b->grp_begin[g];
   }
+  b->table_state_bytes = state_bytes;
   if (n > 0)
     PM_HIP(hipMemcpyAsync(b->pool + b->fx.table, b->stage, (size_t)n * SLOT_DESC, hipMemcpyHostToDevice, b->stream));
   PM_HIP(hipEventRecord(b->stage_done, b->stream));
@@ -246,7 +250,9 @@ template <typename T>
 int iterate_group(pm_batch* b, const Part& pt, hipStream_t st) {
   const int g = pt.g, L = group_L(g), n = pt.n;
   const pm::Slot<T>* tab = dev_table<T>(b, g) + pt.first;
-  const pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_RUNNING, 1.0 / ((double)L * (double)L), nullptr);
+  pm::Extra<T> x = pmh::extra<T>(1, pm::GATE_RUNNING, 1.0 / ((double)L * (double)L), nullptr);
+  // the states of every group share the caches, so the policy follows their total
+  x.stream_state = pmh::stream_state(b->table_state_bytes);
   const pm::Tuning tv = pm::get_tuning(group_fp64(g) ? PM_FP64 : PM_FP32, L);
   PM_HIP(pm::launch_col<T>(L, pm::COL_ALL, tv.col, tab, n, x, st));
   PM_HIP(pm::launch_row<T>(L, pm::ROW_ITER, tv.row, tab, n, x, st));

@@ -92,6 +92,12 @@ pm::Extra<T> extra(int use_state, int gate, double scale, const double* E) {
   return x;
 }
 
+// Whether the iteration streams the stress state past the caches: when the
+// states being iterated together exceed half the 256 MB Infinity Cache they
+// cannot stay there from one pass to the next, and the non-temporal hint
+// keeps them from evicting the spectrum; smaller states are left cached.
+inline int stream_state(size_t state_bytes) { return state_bytes > ((size_t)128 << 20) ? 1 : 0; }
+
 // Host mirror of the device mask generator (SplitMix64 of seed ^ SplitMix64(p)).
 uint64_t splitmix64(uint64_t z);
 

@@ -94,6 +94,7 @@ struct Extra {
   double scale;          // Green-tensor output scale (1/L^2 in the iteration)
   int32_t use_state;     // 1: E from the slot state
   int32_t gate;          // Gate: skip halted slots, or slots without a pending record
+  int32_t stream_state;  // ROW_ITER: stress state loaded and stored with the non-temporal hint
   cx<T>* spec_alt;       // ROW_SIGFWD / column transforms: this spectrum instead of the slot's
 };
 

@@ -509,7 +509,7 @@ __device__ __forceinline__ void stage_pair_out(gptr<cx<T>> __restrict__ g, const
 //   ROW_FWD / ROW_INV  plain row transforms of three real planes (checks)
 //   ROW_SIGFWD forward row transform of the stored stress (11, 22, 12) into
 //             x.spec_alt (the continuum equilibrium indicator of CG1)
-template <typename T, int L, int RMAX, int TEAMS, int WT, int MODE>
+template <typename T, int L, int RMAX, int TEAMS, int WT, int MODE, bool NTS>
 __global__ void __launch_bounds__(TEAMS*(L / RMAX)) __attribute__((amdgpu_waves_per_eu(PM_ROW_WPE)))
 k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   constexpr int TPF = L / RMAX;
@@ -538,14 +538,18 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
   gptr<const cx<T>> __restrict__ tw = glb(S.tw);
   gptr<const uint8_t> __restrict__ mask = glb(S.mask);
   // the stress state: (11, 22, 33, 12) of a pixel side by side, one vector.
-  // The iteration streams it in and out once per pass, and it is larger than
-  // the caches (268 MB at L = 4096 FP32), so those loads and stores carry the
-  // non-temporal hint (measured: the row pass 8 % faster at L = 4096, 4 % at
-  // 8192).  The spectrum keeps the default policy: adjacent row pairs share
-  // its cache lines, and the column pass reads it back from the Infinity
-  // Cache where it fits.
+  // The iteration streams it in and out once per pass.  NTS (set by the host
+  // when the states iterated together exceed half the 256 MB Infinity Cache)
+  // gives those loads and stores the non-temporal hint (measured: the FP32
+  // row pass 8 % faster at L = 4096, 4 % at 8192, the 256-realization batch
+  // 5 %); smaller states keep the default policy, which leaves them in the
+  // cache for the next pass (there the hint cost 7 % at L = 1024 and 2048
+  // FP32, 15-18 % in FP64).  The spectrum always keeps the default policy:
+  // adjacent row pairs share its cache lines, and the column pass reads it
+  // back from the Infinity Cache where it fits.
   using v4 = T __attribute__((ext_vector_type(4)));
   gptr<v4> __restrict__ sig = (gptr<v4>)glb(S.sig);
+  static_assert(!NTS || MODE == ROW_ITER, "the non-temporal state policy belongs to the iteration");
   const Mat<T> m = make_mat<T>(S.prm);
   constexpr unsigned NPX = (unsigned)L * L;
 
@@ -564,7 +568,9 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
       const unsigned ix = (unsigned)(half ? rb : ra) * L + tt + TPF * s;
       if constexpr (MODE != ROW_ITER) mk[s][half] = mask[ix];
       if constexpr (MODE == ROW_ITER) {
-        const v4 q = __builtin_nontemporal_load(sig + ix);
+        v4 q;
+        if constexpr (NTS) q = __builtin_nontemporal_load(sig + ix);
+        else q = sig[ix];
         so[s][half][0] = q.x; so[s][half][1] = q.y; so[s][half][2] = q.z; so[s][half][3] = q.w;
       }
     }
@@ -743,7 +749,9 @@ k_row(const Slot<T>* __restrict__ slots, Extra<T> x) {
           else { e[0] = zb[s].re; e[1] = zb[s].im; e[2] = zc[s].im; }
           pl = alm_point(e, so[s][half], isv, m, en, sg, tau);
         }
-        __builtin_nontemporal_store(v4{sg[0], sg[1], flag33(sg[2], isv), sg[3]}, sig + ix);
+        const v4 snew = {sg[0], sg[1], flag33(sg[2], isv), sg[3]};
+        if constexpr (NTS) __builtin_nontemporal_store(snew, sig + ix);
+        else sig[ix] = snew;
         {
           const double c0 = (double)(e[0] - en[0]), c1 = (double)(e[1] - en[1]), c2 = (double)en[2],
                        c3 = (double)(e[2] - en[3]);
@@ -1077,10 +1085,10 @@ static size_t col_lds() {
   return ColLds<T, L, C::COL_CB, C::COL_TPF>::bytes;
 }
 
-template <typename T, int L, int V, int MODE>
+template <typename T, int L, int V, int MODE, bool NTS = false>
 static hipError_t launch_row_LM(const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
   using C = Cfg<T, L, V>;
-  auto kern = k_row<T, L, C::RMAX, C::ROW_TEAMS, C::COL_W, MODE>;
+  auto kern = k_row<T, L, C::RMAX, C::ROW_TEAMS, C::COL_W, MODE, NTS>;
   static bool attr = false;
   const size_t lds = row_lds<T, L, V>();
   if (!attr) {
@@ -1115,6 +1123,9 @@ template <typename T, int L>
 static hipError_t launch_row_L(int mode, int v, const Slot<T>* slots, int nslots, const Extra<T>& x, hipStream_t st) {
   switch (mode) {
     case ROW_ITER:
+      if (x.stream_state)
+        return v ? launch_row_LM<T, L, 1, ROW_ITER, true>(slots, nslots, x, st)
+                 : launch_row_LM<T, L, 0, ROW_ITER, true>(slots, nslots, x, st);
       return v ? launch_row_LM<T, L, 1, ROW_ITER>(slots, nslots, x, st)
                : launch_row_LM<T, L, 0, ROW_ITER>(slots, nslots, x, st);
     case ROW_INIT: return launch_row_LM<T, L, 0, ROW_INIT>(slots, nslots, x, st);

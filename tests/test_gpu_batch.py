@@ -103,6 +103,38 @@ def test_batch_bitwise_equals_single_solver(tick_iters):
     assert saw == {1, 2}
 
 
+def test_streamed_state_batch_equals_cached_single_solves():
+    """Three L = 2048 FP32 realizations in one batch hold 192 MiB of stress
+    state, above the 128 MiB from which the iteration streams the state with
+    the non-temporal hint; each alone holds 64 MiB and keeps the default
+    cache policy.  The hint changes no arithmetic: records and final fields
+    are bitwise equal."""
+    L = 2048
+    jobs = []
+    for k in range(3):
+        mask = torch.tensor(synth.bernoulli_mask(L, 0.2, 40 + k), device="cuda")
+        path = synth.load_path("shear" if k % 2 else "equibiaxial", 10, 3.0)[:2]
+        jobs.append((mask, params(L, "fp32", tol=0.0, max_iter=12, c0=0.01), path))
+    b = pmb.Batch(pool_for(jobs, 4), max_slots=4)
+    finals = {}
+
+    def grab(i, s):
+        sig, eps, pl, out = b.fetch(s)
+        finals[i] = (sig.clone(), eps.clone(), pl.clone())
+
+    recs = pmb.run_all(b, jobs, tick_iters=5, on_finish=grab)
+    b.close()
+    for i, job in enumerate(jobs):
+        ref = single(job)
+        for rec, r in zip(recs[i], ref):
+            assert rec.iters == 12
+            assert_record_equals(rec, r)
+        sig, eps, pl = finals[i]
+        assert torch.equal(sig, ref[-1].sigma)
+        assert torch.equal(eps, ref[-1].eps)
+        assert torch.equal(pl, ref[-1].plastic)
+
+
 def test_graph_replays_match_eager_ticks():
     """Ticks replayed from a captured graph give the same records as eager
     ticks; admissions and releases between replays force recaptures."""
