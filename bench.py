@@ -656,6 +656,13 @@ def main():
                      "traffic": None if traffic is None else traffic["k_row"],
                      "algorithmic_bytes_per_launch": row_b, "avg_launch_ms": row_avg_ms,
                      "measured_copy_GBs": copy["GBs"], "frac_of_copy": row_gbs / copy["GBs"]},
+        # whole solve against the byte floor of the two-pass design (row pass
+        # + column pass bytes per pixel-iteration), at the peak and at the copy rate
+        "method_floor": {"bytes_per_px_iter": (row_b + col_b) / (L * L),
+                         "ceiling_px_iter_s": HBM_PEAK_GBS * 1e9 * L * L / (row_b + col_b),
+                         "frac_of_ceiling": r32["value"] * (row_b + col_b) / (L * L) / (HBM_PEAK_GBS * 1e9),
+                         "ceiling_at_copy_px_iter_s": copy["GBs"] * 1e9 * L * L / (row_b + col_b),
+                         "frac_of_ceiling_at_copy": r32["value"] * (row_b + col_b) / (L * L) / (copy["GBs"] * 1e9)},
         "kernels": {
             "k_column": {"achieved_GBs": col_gbs, "frac": col_gbs / HBM_PEAK_GBS,
                          "frac_of_copy": col_gbs / copy["GBs"], "avg_launch_ms": col_avg_ms,
