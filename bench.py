@@ -579,7 +579,7 @@ def cpu_baseline(L):
     from oracle import alm
     from paper_0802_2488_amd import synth
 
-    cores = len(os.sched_getaffinity(0))
+    host_cores = len(os.sched_getaffinity(0))
     mask = synth.bernoulli_mask(L, 0.3, 0)
     E = synth.load_path("shear", 40, 4.0)[0]
     s = alm.Solver(mask, alm.Params(L=L))
@@ -590,9 +590,11 @@ def cpu_baseline(L):
         s.iterate(E)
     dt = time.perf_counter() - t0
     del s
-    return dict(value=L * L * n / dt, unit="pixel-iters/s", cores=1, host_cores=cores, kind="oracle",
-                sample=f"{n} augmented-Lagrangian iterations of load step 1 at L={L} (FP64 numpy, "
-                       f"numpy FFT single-threaded; Green tensor setup excluded), {dt:.1f} s")
+    return dict(value=L * L * n / dt, unit="pixel-iters/s", cores=alm.fft_workers(L), host_cores=host_cores,
+                kind="oracle",
+                sample=f"{n} augmented-Lagrangian iterations of load step 1 at L={L} (FP64; scipy.fft on "
+                       f"{alm.fft_workers(L)} threads, pointwise numpy single-threaded; Green tensor setup "
+                       f"excluded), {dt:.1f} s")
 
 
 def main():

@@ -31,10 +31,21 @@ added.  All three must hold at the same iteration (iteration >= 2).
 from __future__ import annotations
 
 import dataclasses
+import os
 
 import numpy as np
+import scipy.fft as sfft
 
 from . import dg, hencky
+
+# FFT threads: the cores this process may run on (the FFT is a library step;
+# the pointwise arithmetic stays plain single-threaded numpy).  Grids below
+# 512 use one thread, where starting threads costs more than it saves.
+FFT_WORKERS = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def fft_workers(L):
+    return FFT_WORKERS if L >= 512 else 1
 
 
 @dataclasses.dataclass
@@ -101,7 +112,7 @@ def mean_div2_continuum(sig):
     DFT: the mean over the pixels is the sum over the modes divided by L^4.
     """
     L = sig.shape[0]
-    S = np.fft.fft2(sig[..., :2, :2], axes=(0, 1))
+    S = sfft.fft2(sig[..., :2, :2], axes=(0, 1), workers=fft_workers(L))
     xi = dg.frequencies(L)
     keep = np.arange(L) != L // 2
     x1 = xi[None, :]
@@ -118,7 +129,7 @@ def divergence_fourier(sig):
     <|div|^2> = sum_q |conj(k_l) sigma_kl(q)|^2 / L^4 (full spectrum).
     """
     L = sig.shape[0]
-    S = np.fft.fft2(sig[..., :2, :2], axes=(0, 1))
+    S = sfft.fft2(sig[..., :2, :2], axes=(0, 1), workers=fft_workers(L))
     k1 = dg.wave_vector(L)[None, :]
     k2 = dg.wave_vector(L)[:, None]
     v = np.conj(k1)[..., None] * S[..., :, 0] + np.conj(k2)[..., None] * S[..., :, 1]
@@ -164,10 +175,10 @@ class Solver:
     def green_step(self, tau, E):
         """e = E + G * tau (step (a)); tau and e are (L, L, 3, 3), e33 = 0."""
         L = self.p.L
-        t_hat = np.fft.rfft2(tau[..., :2, :2], axes=(0, 1))
+        t_hat = sfft.rfft2(tau[..., :2, :2], axes=(0, 1), workers=fft_workers(L))
         e_hat = dg.apply_green(self.G, t_hat)
         e_hat[0, 0] = tensor_from_voigt(E)[:2, :2] * (L * L)
-        e2 = np.fft.irfft2(e_hat, s=(L, L), axes=(0, 1))
+        e2 = sfft.irfft2(e_hat, s=(L, L), axes=(0, 1), workers=fft_workers(L))
         e = np.zeros((L, L, 3, 3))
         e[..., :2, :2] = e2
         return e

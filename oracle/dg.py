@@ -10,7 +10,7 @@ f(x) - f(x - e^j) becomes i conj(k_j) f(q).
 
 Array layout: real fields are indexed [x2][x1] (x1 is the contiguous axis and
 the direction of e^1); tensor index 0 is direction 1 and index 1 is
-direction 2.  Half spectra from numpy.fft.rfft2 over axes (0, 1) are indexed
+direction 2.  Half spectra from a real 2-D FFT over axes (0, 1) are indexed
 [m2][m1] with m1 = 0..L/2.
 """
 from __future__ import annotations
