@@ -91,7 +91,8 @@ def green_dg1_on_grid(L: int, lam0: float, mu0: float) -> np.ndarray:
     """Symmetrised DG1 tensor of eq. 4 on the half spectrum.
 
     G1 = {G(q1,q2) + G(-q1,-q2) + (-1)^(i+j+k+l) [G(-q1,q2) + G(q1,-q2)]} / 4.
-    Parity unpinned beyond the properties tested (real valued, symmetries).
+    Pinned by hand-derived closed forms at the self-conjugate points (pi, 0)
+    and (pi, pi), by being real valued and by its mirror symmetry.
     """
     G0, G1, G2, G3 = (green_on_grid(L, lam0, mu0, v) for v in range(4))
     idx = np.indices((2, 2, 2, 2)).sum(axis=0)   # i+j+k+l with 0-based indices

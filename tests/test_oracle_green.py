@@ -148,6 +148,39 @@ def test_dg1_is_real():
     assert np.abs(G1.imag).max() < 1e-15
 
 
+@pytest.mark.parametrize("lam0,mu0", [(LAM0, MU0), (0.7, 0.3)])
+def test_green_and_dg1_closed_forms_at_nyquist_points(lam0, mu0):
+    """Hand-derived values at the self-conjugate points q = (pi, 0) and
+    (pi, pi), where k = 2i on each Nyquist axis and k(-q) = -conj k(q) = k(q),
+    so the four sign variants coincide.
+
+    q = (pi, 0), k = (2i, 0): the acoustic tensor is diag(4 lam0 + 8 mu0,
+    4 mu0); a unit hydrostatic tau gives eps11 = -1/(lam0 + 2 mu0) (the
+    longitudinal wave) and nothing else, a unit tau12 gives eps12 =
+    -1/(2 mu0) (the transverse wave).  q = (pi, pi), k = 2i (1, 1): a unit
+    hydrostatic tau gives eps11 = eps22 = eps12 = -1/(2 (lam0 + 2 mu0)) with
+    eq. 3; in DG1 the sign (-1)^(i+j+k+l) of the two mixed variants cancels
+    the eps12 response to the diagonal of tau, and keeps the rest.
+    """
+    L = 8
+    h = L // 2
+    G = dg.green_on_grid(L, lam0, mu0, 0)
+    G1 = dg.green_dg1_on_grid(L, lam0, mu0)
+    hyd = np.eye(2)
+    shear = np.array([[0.0, 1.0], [1.0, 0.0]])
+
+    def apply(T, m2, m1, tau):
+        return np.einsum("ijkl,kl->ij", T[m2, m1], tau)
+
+    long_ = -1.0 / (lam0 + 2.0 * mu0)
+    for T in (G, G1):
+        np.testing.assert_allclose(apply(T, 0, h, hyd), [[long_, 0.0], [0.0, 0.0]], atol=1e-14)
+        np.testing.assert_allclose(apply(T, 0, h, shear), [[0.0, -0.5 / mu0], [-0.5 / mu0, 0.0]], atol=1e-14)
+    diag = -0.5 / (lam0 + 2.0 * mu0)
+    np.testing.assert_allclose(apply(G, h, h, hyd), [[diag, diag], [diag, diag]], atol=1e-14)
+    np.testing.assert_allclose(apply(G1, h, h, hyd), [[diag, 0.0], [0.0, diag]], atol=1e-14)
+
+
 def test_fourier_divergence_equals_real_space():
     """The paper evaluates <|div sigma|^2> in Fourier space; Parseval makes it
     equal to the real-space backward-difference form."""
