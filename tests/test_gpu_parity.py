@@ -368,6 +368,26 @@ def test_homogeneous_medium_exact():
         assert np.abs(s - ref[:, None, None]).max() <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
+def test_all_void_grid(precision, tol):
+    """f = 1: the closed form of the oracle's pin (sigma = 0, eps = E with
+    eps33 = 0, converged at iteration 2 with all indicators 0); the strain
+    output is recovered from the polarisation after a row transform, hence
+    the rounding allowance."""
+    L = 64
+    g = pms.Solver(torch.ones((L, L), dtype=torch.uint8, device="cuda"), gpu_params(L, precision, c0=0.02, tol=1e-8))
+    for E in ((0.3, 0.1, 0.05), (0.0, 0.0, 0.4)):
+        r = g.step(E)
+        assert r.converged and r.iters == 2
+        assert r.res_eq == 0.0 and r.res_mac == 0.0 and r.res_cmp == 0.0
+        assert float(r.sigma.abs().max()) == 0.0
+        eps = r.eps.cpu().double().numpy()
+        ref = np.array([E[0], E[1], 0.0, E[2]])
+        assert np.abs(eps - ref[:, None, None]).max() <= tol * np.abs(ref).max()
+        assert int(r.plastic.sum()) == 0
+    g.close()
+
+
 def test_zero_load_and_restart():
     L = 32
     mask = synth.bernoulli_mask(L, 0.2, 1)

@@ -44,6 +44,21 @@ def test_homogeneous_medium_is_uniform_after_one_iteration(E):
     assert r.converged and r.iters == 2
 
 
+@pytest.mark.parametrize("E", [(0.3, 0.1, 0.05), (0.0, 0.0, 0.4)])
+def test_all_void_grid_carries_the_mean_strain_and_no_stress(E):
+    """f = 1: no pixel has stiffness, so sigma = 0 everywhere, nothing drives
+    a fluctuation and eps = E with eps33 = 0 (a void's out-of-plane strain);
+    every indicator is 0 against its norm floor and the step converges at
+    the first iteration where the test applies."""
+    L = 16
+    r = alm.Solver(np.ones((L, L), np.uint8), _params(L, c0=0.02)).step(E)
+    assert r.converged and r.iters == 2
+    assert r.res_eq == 0.0 and r.res_mac == 0.0 and r.res_cmp == 0.0
+    assert np.all(r.sigma == 0.0)
+    np.testing.assert_allclose(r.eps, np.broadcast_to(alm.tensor_from_voigt(E), r.eps.shape), atol=1e-15)
+    assert not r.plastic.any()
+
+
 def test_zero_load_gives_zero_solution():
     mask = synth.bernoulli_mask(8, 0.2, 0)
     s = alm.Solver(mask, _params(8))
