@@ -103,6 +103,33 @@ def nearest_void(L, pixels, void_idx):
     return int(best), int(v)
 
 
+def nearest_void_local(L, pixels, void_flat, r_max=64):
+    """The result of nearest_void, from the voids near the cluster only.
+
+    Offsets (oy, ox) with |oy|, |ox| <= r around every cluster pixel are
+    searched, r = 1, 2, 4, ...; a void at periodic distance d <= r from some
+    cluster pixel lies in that pixel's window, so once the smallest squared
+    offset found is <= r^2 it is the distance to the cluster and every void
+    at that distance is among the candidates (ties to the smallest index as
+    in nearest_void).  For r < L / 2 every offset is its own minimal periodic
+    image.  Beyond r_max (very sparse voids) it defers to nearest_void."""
+    py, px = np.divmod(np.asarray(pixels, dtype=np.int64), L)
+    r = 1
+    while 2 * r < L and r <= r_max:
+        off = np.arange(-r, r + 1)
+        oy, ox = np.meshgrid(off, off, indexing="ij")
+        oy, ox = oy.ravel(), ox.ravel()
+        vid = ((py[:, None] + oy[None, :]) % L) * L + (px[:, None] + ox[None, :]) % L
+        d2 = np.broadcast_to(oy * oy + ox * ox, vid.shape)
+        hit = void_flat[vid]
+        if hit.any():
+            best = int(d2[hit].min())
+            if best <= r * r:
+                return best, int(vid[hit & (d2 == best)].min())
+        r *= 2
+    return nearest_void(L, pixels, np.flatnonzero(void_flat))
+
+
 def analyze(void: np.ndarray, plastic: np.ndarray):
     """Cluster labels (after attachment) and the counts behind the indicators."""
     void = np.asarray(void).astype(bool)
@@ -115,9 +142,14 @@ def analyze(void: np.ndarray, plastic: np.ndarray):
     roots = np.unique(raw[raw >= 0])
     flat = raw.ravel()
     vflat, pflat = void.ravel(), plastic.ravel()
-    has_void = {int(r): bool(vflat[flat == r].any()) for r in roots}
-    has_plastic = {int(r): bool(pflat[flat == r].any()) for r in roots}
-    void_idx = np.flatnonzero(vflat)
+    # raw labels are pixel indices: flag the clusters holding a void / a plastic pixel
+    has_void = np.zeros(npx, dtype=bool)
+    has_void[flat[vflat]] = True
+    has_plastic = np.zeros(npx, dtype=bool)
+    has_plastic[flat[pflat]] = True
+    # the pixels of every raw cluster, grouped
+    order = np.argsort(flat, kind="stable")
+    sorted_lab = flat[order]
     # attach plastic-only clusters to the cluster of their nearest void
     parent = {int(r): int(r) for r in roots}
 
@@ -126,20 +158,24 @@ def analyze(void: np.ndarray, plastic: np.ndarray):
             x = parent[x]
         return x
 
-    plastic_only = [int(r) for r in roots if not has_void[int(r)]]
-    if len(void_idx):
+    plastic_only = [int(r) for r in roots if not has_void[r]]
+    if vflat.any():
         for r in plastic_only:
-            _, v = nearest_void(L, np.flatnonzero(flat == r), void_idx)
+            lo, hi = np.searchsorted(sorted_lab, [r, r + 1])
+            _, v = nearest_void_local(L, order[lo:hi], vflat)
             a, b = find(r), find(int(flat[v]))
             if a != b:
                 parent[max(a, b)] = min(a, b)
-    final = np.full(npx, -1, dtype=np.int64)
-    comp = np.array([find(int(x)) if x >= 0 else -1 for x in flat])
-    inside = comp >= 0
+    rep = np.full(npx, -1, dtype=np.int64)
+    for r in roots:
+        rep[r] = find(int(r))
+    inside = flat >= 0
+    comp = np.where(inside, rep[np.where(inside, flat, 0)], -1)
     # canonical labels again: smallest pixel index of each merged component
-    for c in np.unique(comp[inside]):
-        sel = comp == c
-        final[sel] = np.flatnonzero(sel).min()
+    mins = np.full(npx, npx, dtype=np.int64)
+    np.minimum.at(mins, comp[inside], np.flatnonzero(inside))
+    final = np.full(npx, -1, dtype=np.int64)
+    final[inside] = mins[comp[inside]]
     final = final.reshape(L, L)
     labs, sizes = np.unique(final[final >= 0], return_counts=True)
     if len(labs):
@@ -155,7 +191,7 @@ def analyze(void: np.ndarray, plastic: np.ndarray):
         n_void=int(void.sum()), n_plastic=int(plastic.sum()),
         n_void_clusters=n_void_clusters,
         n_clusters_raw=len(roots),
-        n_isolated_void_clusters=sum(1 for r in roots if has_void[int(r)] and not has_plastic[int(r)]),
+        n_isolated_void_clusters=int(np.count_nonzero(has_void[roots] & ~has_plastic[roots])),
         n_plastic_only_clusters=len(plastic_only),
         n_clusters=len(labs), largest=int(big), largest_label=largest_label,
         spans_x1=spans_x1, spans_x2=spans_x2,

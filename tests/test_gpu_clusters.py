@@ -47,6 +47,19 @@ def test_random_phases_bit_exact(L, fv, fp, seed):
     assert st["n_clusters"] == st["n_clusters_raw"] - st["n_plastic_only_clusters"]
 
 
+@pytest.mark.parametrize("L,fv,fp,seed", [(4096, 0.3, 0.05, 11), (2048, 0.1, 0.6, 13)])
+def test_full_size_bit_exact(L, fv, fp, seed):
+    """The benchmark's size and void fraction with a sparse plastic phase, and
+    a grid whose void-plastic phase (0.1 + 0.54 of the sites) lies past the
+    square lattice's site-percolation threshold (0.593), so one cluster spans
+    the cell."""
+    void = synth.bernoulli_mask(L, fv, seed).astype(bool)
+    plastic = synth.bernoulli_mask(L, fp, 1000 + seed).astype(bool) & ~void
+    st = check(void, plastic)
+    if fp == 0.6:
+        assert st["spans_x1"] and st["spans_x2"]
+
+
 def test_plastic_mask_of_a_solve():
     L = 128
     mask = synth.bernoulli_mask(L, 0.1, 0)

@@ -80,6 +80,79 @@ def test_attachment_tie_goes_to_the_smaller_void_index():
     assert lab[4, 4] == 4 * L + 1
 
 
+def _analyze_by_definition(void, plastic):
+    """Slow reference of clusters.analyze for small grids: breadth-first
+    labels, one scan per cluster, the brute-force nearest void."""
+    L = void.shape[0]
+    npx = L * L
+    raw = clusters.label_bfs(void | plastic).ravel()
+    vflat, pflat = void.ravel(), plastic.ravel()
+    roots = sorted(set(int(x) for x in raw if x >= 0))
+    void_idx = np.flatnonzero(vflat)
+    parent = {r: r for r in roots}
+
+    def find(x):
+        while parent[x] != x:
+            x = parent[x]
+        return x
+
+    only = [r for r in roots if not vflat[raw == r].any()]
+    if len(void_idx):
+        for r in only:
+            _, v = clusters.nearest_void(L, np.flatnonzero(raw == r), void_idx)
+            a, b = find(r), find(int(raw[v]))
+            if a != b:
+                parent[max(a, b)] = min(a, b)
+    comp = np.array([find(int(x)) if x >= 0 else -1 for x in raw])
+    final = np.full(npx, -1, dtype=np.int64)
+    for c in set(comp[comp >= 0].tolist()):
+        final[comp == c] = np.flatnonzero(comp == c).min()
+    isolated = sum(1 for r in roots if vflat[raw == r].any() and not pflat[raw == r].any())
+    return final.reshape(L, L), len(only), isolated
+
+
+@pytest.mark.parametrize("L,fv,fp,seed", [(8, 0.1, 0.4, 0), (16, 0.05, 0.3, 1), (16, 0.02, 0.5, 2),
+                                          (32, 0.03, 0.45, 3), (32, 0.005, 0.3, 4), (24, 0.2, 0.2, 5)])
+def test_analyze_equals_its_definition(L, fv, fp, seed):
+    """The grouped, vectorised analysis against the plain per-cluster one."""
+    void = synth.bernoulli_mask(L, fv, seed).astype(bool)
+    plastic = synth.bernoulli_mask(L, fp, 500 + seed).astype(bool) & ~void
+    lab, st = clusters.analyze(void, plastic)
+    ref, n_only, isolated = _analyze_by_definition(void, plastic)
+    assert np.array_equal(lab, ref)
+    assert st["n_plastic_only_clusters"] == n_only and st["n_isolated_void_clusters"] == isolated
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_local_nearest_void_equals_brute_force(seed):
+    """Windowed search against the full distance scan, with ties: sparse and
+    dense voids, clusters across the periodic edge, lattice-symmetric voids."""
+    tie = np.zeros((16, 16), dtype=bool)
+    tie[5, 2] = tie[5, 8] = True   # both 3 pixels from (5, 5): the smaller index wins
+    assert clusters.nearest_void_local(16, np.array([5 * 16 + 5]), tie.ravel()) == (9, 5 * 16 + 2)
+    rng = np.random.default_rng(seed)
+    L = int(rng.choice([8, 16, 32, 64]))
+    void = rng.random((L, L)) < rng.choice([0.003, 0.02, 0.2])
+    if seed % 3 == 0:   # symmetric pair of voids around a pixel: an exact tie
+        void[:] = False
+        c = int(rng.integers(L))
+        void[c, (c + 3) % L] = void[c, (c - 3) % L] = True
+    if not void.any():
+        void[0, 0] = True
+    free = np.flatnonzero(~void.ravel())
+    for k in (1, 3, 12):
+        start = int(rng.choice(free))
+        y, x = divmod(start, L)
+        pix = {start}
+        for _ in range(k - 1):   # a random walk, wrapping around the edges
+            y, x = (y + int(rng.integers(-1, 2))) % L, (x + int(rng.integers(-1, 2))) % L
+            if not void[y, x]:
+                pix.add(y * L + x)
+        pix = np.array(sorted(pix))
+        assert clusters.nearest_void_local(L, pix, void.ravel()) == \
+            clusters.nearest_void(L, pix, np.flatnonzero(void.ravel()))
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_counting_identities_and_symmetries(seed):
     L = 32
