@@ -38,3 +38,14 @@ def test_source_digest_ignores_comments_but_not_code(tmp_path, monkeypatch):
     k.write_text(text.replace("#define PM_ROW_PREFETCH 2", "#define PM_ROW_PREFETCH 3"))
     assert bench.kernel_sources_digest() != d0
 
+
+
+def test_committed_counters_describe_the_current_kernels():
+    """The counter summary under profiles/ was taken from the kernels as they
+    are (its recorded source digest matches), and its HBM bytes per launch
+    are within 20 % above the algorithmic bytes of each pass."""
+    t = bench.measured_traffic()
+    assert t is not None, "kernel sources changed since the counter summary was taken"
+    row, col = bench.algorithmic_bytes(4096, 4)
+    assert 1.0 <= t["k_row"] / row <= 1.2
+    assert 1.0 <= t["k_column"] / col <= 1.2
