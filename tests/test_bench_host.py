@@ -39,7 +39,6 @@ def test_source_digest_ignores_comments_but_not_code(tmp_path, monkeypatch):
     assert bench.kernel_sources_digest() != d0
 
 
-
 def test_committed_counters_describe_the_current_kernels():
     """The counter summary under profiles/ was taken from the kernels as they
     are (its recorded source digest matches), and its HBM bytes per launch
