@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--no-next", action="store_true", help="skip the DG2 / cluster / method measurements")
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--batch-max-iter", type=int, default=500)
+    ap.add_argument("--batch-conv-max-iter", type=int, default=20000,
+                    help="iteration limit of the batched workload run to the tolerance (FP64)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-n", type=int, default=200, help="requests of the serving trace")
     ap.add_argument("--serve-max-iter", type=int, default=200)
@@ -217,8 +219,8 @@ def copy_bandwidth():
     return {"what": "device-to-device copy of 1 GiB (torch copy_), best of 6", "GBs": 2 * 4 * n / (best * 1e-3) / 1e9}
 
 
-def batch_jobs(n, max_iter):
-    """The uneven batched workload: masks on the device, FP32, tol 1e-6."""
+def batch_jobs(n, max_iter, precision="fp32"):
+    """The uneven batched workload: masks on the device, tol 1e-6."""
     from paper_0802_2488_amd import solver as pms
     from paper_0802_2488_amd import synth
 
@@ -227,10 +229,16 @@ def batch_jobs(n, max_iter):
         mask = pms.device_mask(r["L"], r["f"], r["seed"])
         c0 = synth.C0_SOFT
         params = pms.make_params(r["L"], mu=1.0, lam=2.0, Y=1.0, mu0=c0, lam0=2.0 * c0, tol=1e-6, max_iter=max_iter,
-                                 precision="fp32")
+                                 precision=precision)
         path = synth.load_path(r["kind"], r["steps"], synth.default_emax(r["kind"], 1.0, 1.0))
         jobs.append((mask, params, path))
     return jobs
+
+
+def synth_realizations(n):
+    from paper_0802_2488_amd import synth
+
+    return list(synth.batch_realizations(n))
 
 
 def run_batch(jobs, tick):
@@ -249,7 +257,7 @@ def run_batch(jobs, tick):
     work = sum(j[1].L ** 2 * sum(r.iters for r in rr) for j, rr in zip(jobs, recs))
     return dict(value=work / dt, seconds=dt, pixel_iters=work, pool_bytes=pool,
                 converged_steps=sum(r.status == 1 for rr in recs for r in rr),
-                steps=sum(len(rr) for rr in recs))
+                steps=sum(len(rr) for rr in recs), recs=recs)
 
 
 def run_sequential(jobs):
@@ -291,6 +299,18 @@ def batched_section(a):
     sb = run_batch(sample, a.tick)
     sq = run_sequential(sample)
     print(f"# sequential sample done: {sq['value']:.4e} px-iter/s", file=sys.stderr, flush=True)
+    # the same realizations run to the tolerance: FP64 (the FP32 primal
+    # residual has a floor above 1e-6 at these loads), first 2 load steps
+    conv = run_batch([(m, p, path[:2]) for m, p, path in batch_jobs(a.batch_n, a.batch_conv_max_iter, "fp64")], 64)
+    real = synth_realizations(a.batch_n)
+    by_f = {}
+    for lo, hi in ((0.05, 0.15), (0.15, 0.25), (0.25, 0.35), (0.35, 0.4)):
+        sel = [rr for r, rr in zip(real, conv["recs"]) if lo <= r["f"] < hi or (hi == 0.4 and r["f"] >= hi)]
+        n = sum(len(rr) for rr in sel)
+        by_f[f"{lo}-{hi}"] = {"steps": n, "converged_fraction": sum(x.status == 1 for rr in sel for x in rr) / max(n, 1)}
+    its = sorted(x.iters for rr in conv["recs"] for x in rr if x.status == 1)
+    print(f"# batched to tolerance done: {conv['converged_steps']}/{conv['steps']} steps in {conv['seconds']:.1f} s",
+          file=sys.stderr, flush=True)
     return {
         "workload": f"{a.batch_n} realizations (seed 1000 + r, L uniform on {{128, 256, 512}}, f ~ U[0.05, 0.4], "
                     f"even r equibiaxial to 3Y/mu, odd r shear to 4Y/mu, 20 load steps, tol 1e-6, FP32, "
@@ -304,6 +324,14 @@ def batched_section(a):
         "same_work_sample": {"what": f"all {len(jobs)} realizations, load steps 1-2",
                              "batched": sb["value"], "sequential": sq["value"],
                              "speedup": sb["value"] / sq["value"]},
+        "to_tolerance": {"what": f"all {a.batch_n} realizations, load steps 1-2, FP64, tol 1e-6 on all three "
+                                 f"indicators, max_iter {a.batch_conv_max_iter}, 64 iterations per tick",
+                         "value": conv["value"], "seconds": conv["seconds"], "steps": conv["steps"],
+                         "converged_fraction": conv["converged_steps"] / max(conv["steps"], 1),
+                         "converged_fraction_by_f": by_f,
+                         "iters_of_converged_steps": {"p50": its[len(its) // 2] if its else None,
+                                                      "p90": its[(9 * len(its)) // 10] if its else None,
+                                                      "max": its[-1] if its else None}},
     }
 
 
