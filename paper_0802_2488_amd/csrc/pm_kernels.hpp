@@ -9,8 +9,11 @@
 //                 voids stress free), new polarisation tau, forward real FFT
 //                 back into the row spectra; FP64 partial sums   (k_row)
 //   reductions  : fixed-order FP64 sums, convergence indicators, and the
-//                 backward-difference equilibrium residual when the other two
-//                 indicators already pass                      (k_reduce*, k_div)
+//                 equilibrium residual, with the divergence that belongs to
+//                 the Green tensor in use (backward differences of eq. 1,
+//                 forward ones along a DG2 variant's flipped directions, the
+//                 continuum form for CG1), when the other two indicators
+//                 already pass                  (k_reduce*, k_div, k_div_continuum)
 // The persistent state is the stress of the last iterate ((11, 22, 33, 12)
 // of each pixel side by side), which is also the augmented-Lagrangian
 // multiplier, and the half
