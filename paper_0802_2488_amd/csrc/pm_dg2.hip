@@ -162,6 +162,8 @@ namespace pm {
 // field that varies along one axis only and is 4 b for an oscillation
 // b (-1)^(x1 + x2), so it picks out the checkerboard pattern.
 constexpr int MAP_NSUM = 6;    // sum eps_eq, matrix pixels, sum d^2, blocks, sum diff^2, pairs
+// a block's partials and the final values each take one 8-double record
+static_assert(MAP_NSUM + 1 <= 8, "the map partials records hold 8 doubles");
 
 template <typename T>
 __device__ __forceinline__ double eps_eq_at(gptr<const T> e, long npx, long p) {
