@@ -93,7 +93,9 @@ def parse():
     ap.add_argument("--serve-n", type=int, default=200, help="requests of the serving trace")
     ap.add_argument("--serve-max-iter", type=int, default=200)
     ap.add_argument("--serve-pool-gb", type=float, default=16.0)
-    ap.add_argument("--tick", type=int, default=16, help="iterations per batch tick")
+    ap.add_argument("--tick", type=int, default=16, help="iterations per batch tick of the serving loop")
+    ap.add_argument("--batch-tick", type=int, default=0,
+                    help="iterations per tick of the batched workload (0: the iteration limit, one graph per load step)")
     return ap.parse_args()
 
 
@@ -292,11 +294,12 @@ def autotune_sizes(sizes, precision="fp32"):
 def batched_section(a):
     tuning = autotune_sizes((128, 256, 512))
     jobs = batch_jobs(a.batch_n, a.batch_max_iter)
-    full = run_batch(jobs, a.tick)
+    tick = a.batch_tick or a.batch_max_iter
+    full = run_batch(jobs, tick)
     print(f"# batched done: {full['value']:.4e} px-iter/s in {full['seconds']:.1f} s", file=sys.stderr, flush=True)
     # same-work comparison on every realization of the workload, first 2 load steps
     sample = [(m, p, path[:2]) for m, p, path in jobs]
-    sb = run_batch(sample, a.tick)
+    sb = run_batch(sample, tick)
     sq = run_sequential(sample)
     print(f"# sequential sample done: {sq['value']:.4e} px-iter/s", file=sys.stderr, flush=True)
     # the same realizations run to the tolerance: FP64 (the FP32 primal
@@ -315,7 +318,8 @@ def batched_section(a):
         "workload": f"{a.batch_n} realizations (seed 1000 + r, L uniform on {{128, 256, 512}}, f ~ U[0.05, 0.4], "
                     f"even r equibiaxial to 3Y/mu, odd r shear to 4Y/mu, 20 load steps, tol 1e-6, FP32, "
                     f"reference medium 0.01 x matrix, max_iter {a.batch_max_iter}), one batch, "
-                    f"{a.tick} iterations per tick",
+                    f"{tick} iterations per tick"
+                    + (" (one graph per load step)" if tick == a.batch_max_iter else ""),
         "value": full["value"], "unit": "pixel-iters/s", "seconds": full["seconds"],
         "pixel_iters": full["pixel_iters"], "steps": full["steps"], "converged_steps": full["converged_steps"],
         "converged_fraction": full["converged_steps"] / max(full["steps"], 1),
