@@ -96,3 +96,33 @@ def test_circular_void_cell(L, f):
     # one 4-connected cluster
     from scipy import ndimage
     assert ndimage.label(m)[1] == 1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without libpm.so the product path raises: there is no fallback."""
+    import subprocess
+    import sys
+
+    code = (
+        "from paper_0802_2488_amd import _lib\n"
+        "try:\n"
+        "    _lib.lib()\n"
+        "except RuntimeError as e:\n"
+        "    assert 'missing' in str(e), e\n"
+        "    print('raised')\n"
+        "else:\n"
+        "    raise SystemExit('no error')\n"
+        "import numpy as np\n"
+        "from paper_0802_2488_amd import solver\n"
+        "try:\n"
+        "    solver.Solver(np.zeros((8, 8), np.uint8), solver.make_params(8))\n"
+        "except RuntimeError:\n"
+        "    print('raised')\n"
+        "else:\n"
+        "    raise SystemExit('solver built without the library')\n"
+    )
+    env = dict(os.environ, PM_LIB_PATH=str(tmp_path / "absent" / "libpm.so"))
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["raised", "raised"]
